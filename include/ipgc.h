@@ -1,0 +1,160 @@
+/*
+ * ipgc.h -- C ABI of the MI355X (gfx950) graph-coloring library.
+ *
+ * The library colors an undirected graph with IPGC, Iterative Parallel Graph
+ * Coloring, as described in Section II-C of Rai, M P, Pai, "A Hybrid Graph
+ * Coloring Algorithm for GPUs" (arXiv 1912.01478).  Each round assigns every
+ * uncolored node the smallest color its colored neighbours do not hold, then
+ * uncolors one endpoint of every edge whose endpoints picked the same color.
+ * It repeats until no node is uncolored.  Rounds run either topology-driven
+ * (a sweep over all nodes) or data-driven (over the worklist of uncolored
+ * nodes).  The hybrid schedule of Section IV keeps the worklist in both kinds
+ * of round and picks the kind from the worklist size against a threshold H.
+ *
+ * Semantics are fixed so that the result is deterministic and identical for
+ * every schedule (Section V: all versions run the same algorithm and give the
+ * same colors):
+ *   - colors are 1-based; 0 never appears in the output;
+ *   - rounds are synchronous: assignments read the colors committed before the
+ *     round, and conflict tests read all of the round's tentative colors;
+ *   - on a conflict the endpoint with the lower node id keeps its color;
+ *   - a round is topology-driven iff the worklist size |WL| > H.
+ * The output satisfies 1 <= color[v] <= deg(v) + 1, and the colors used are
+ * exactly 1..max(color).
+ *
+ * Graph format: symmetric CSR with int32 row pointers (n + 1 entries, rowptr[0]
+ * = 0, rowptr[n] = m) and int32 column indices (m entries, each in [0, n)),
+ * where m counts both directions of every edge.  Self-loops and duplicate
+ * entries change nothing in the result.  If every row is sorted ascending, the
+ * library detects that and lets conflict scans stop at the first neighbour id
+ * that is not smaller than the node's own.
+ *
+ * Threads: calls are serialized per device inside the library, which keeps
+ * one cached workspace per device.  All functions return IPGC_OK (0) or a
+ * negative ipgc_status; ipgc_last_error() then describes the failure.
+ */
+#ifndef IPGC_H
+#define IPGC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ipgc_status {
+    IPGC_OK = 0,
+    IPGC_EINVAL = -1,   /* null pointer with n > 0, n < 0, m < 0, bad mode or options */
+    IPGC_ETOOBIG = -2,  /* n or m does not fit the int32 CSR */
+    IPGC_EBADCSR = -3,  /* rowptr[0] != 0, rowptr[n] != m, decreasing rowptr, or id out of [0, n) */
+    IPGC_ENOMEM = -4,   /* device workspace allocation failed */
+    IPGC_EHIP = -5,     /* a HIP runtime call failed */
+    IPGC_ELIMIT = -6    /* the round limit was reached (cannot happen for valid input: rounds <= n) */
+} ipgc_status;
+
+/* Round schedules (Section IV).  TOPOLOGY runs every round as a sweep over all
+ * nodes, DATA runs every round over the worklist, HYBRID picks per round with
+ * the threshold H.  All three push the nodes that lose a conflict onto the
+ * worklist, and all three give the same colors and round count. */
+typedef enum ipgc_mode {
+    IPGC_MODE_TOPOLOGY = 0,
+    IPGC_MODE_DATA = 1,
+    IPGC_MODE_HYBRID = 2
+} ipgc_mode;
+
+/* Validation levels.  A column id outside [0, n) would make the kernels read
+ * outside the color array, so the default checks every id. */
+enum {
+    IPGC_VALIDATE_DEFAULT = 0, /* same as IPGC_VALIDATE_RANGES */
+    IPGC_VALIDATE_NONE = 1,    /* trust the caller: only rowptr[0] == 0 and rowptr[n] == m are checked */
+    IPGC_VALIDATE_RANGES = 2   /* also rowptr non-decreasing and every column id in [0, n) */
+};
+
+/* Kernel kinds that ipgc_profile can time (see ipgc_kernel_name). */
+#define IPGC_PROFILE_KINDS 16
+
+/* Optional device-time profile of one call.  Kernel kinds whose bit is set in
+ * `mask` are bracketed by HIP events recorded on the call's stream; the event
+ * times, launch counts and the work units each kind processed are summed here.
+ * Work units: `nodes` = active nodes handled (a topology sweep's inactive nodes
+ * are not counted), `edges` = row entries of those nodes (their degree sum).
+ * Host memory owned by the caller; the out fields are overwritten. */
+typedef struct ipgc_profile {
+    uint32_t mask;                            /* in: bit k times kernel kind k */
+    int32_t kinds;                            /* out: number of kinds defined */
+    double ms[IPGC_PROFILE_KINDS];            /* out: summed event time per kind */
+    int64_t launches[IPGC_PROFILE_KINDS];     /* out: timed launches per kind */
+    int64_t nodes[IPGC_PROFILE_KINDS];        /* out: active nodes processed per kind (all launches) */
+    int64_t edges[IPGC_PROFILE_KINDS];        /* out: row entries of those nodes per kind */
+} ipgc_profile;
+
+/* Tuning options.  A zeroed struct (or NULL) selects every default.  No option
+ * changes the result, only the time. */
+typedef struct ipgc_options {
+    int64_t threshold;         /* H for HYBRID (topology round iff |WL| > H); 0 or less: floor(6n/10), the
+                                  paper's 60% of the node count.  Ignored by TOPOLOGY and DATA. */
+    int32_t light_max_degree;  /* nodes with degree <= this run thread-per-node (1..63; 0: default 32) */
+    int32_t wave_max_degree;   /* nodes with degree <= this run wavefront-per-node; larger ones run
+                                  workgroup-per-node (light_max_degree+1 .. 2047; 0: default 1024) */
+    int32_t validate;          /* IPGC_VALIDATE_* */
+    int32_t reserved;          /* must be 0 */
+    ipgc_profile *profile;     /* optional per-kernel timing (NULL: none) */
+} ipgc_options;
+
+/* Per-round record, filled on request.  Host memory owned by the caller. */
+typedef struct ipgc_trace {
+    int64_t capacity;    /* entries available in each array below */
+    int32_t *wl_size;    /* |WL_r| at the start of round r (r = 0 .. rounds-1), may be NULL */
+    int64_t *wl_degree;  /* sum of the degrees of the nodes in WL_r, may be NULL */
+    int8_t *topology;    /* 1 if round r ran topology-driven, 0 if data-driven, may be NULL */
+    int64_t recorded;    /* out: min(rounds, capacity) */
+} ipgc_trace;
+
+/*
+ * Color a graph (Section II-C, schedule of Section IV).
+ *
+ * csr_rowptr  DEVICE pointer, n + 1 int32 entries (caller-owned, read only).
+ * csr_colidx  DEVICE pointer, m int32 entries (caller-owned, read only).
+ * n, m        node count and CSR entry count; 0 <= n < 2^31 - 1, 0 <= m < 2^31.
+ * mode        an ipgc_mode.
+ * out_colors  DEVICE pointer, n int32 entries (caller-owned).  The library uses
+ *             it as its color state during the run; on success it holds the
+ *             final 1-based colors.  On error its contents are unspecified.
+ * out_rounds  HOST pointer: number of rounds run (-1 on error).
+ *
+ * Blocks until the colors are in out_colors.  Runs on the device that is
+ * current for the calling thread, on its null stream.  n = 0 succeeds with
+ * zero rounds.  The library keeps no caller pointer after returning.
+ */
+int ipgc_color_graph(const int32_t *csr_rowptr, const int32_t *csr_colidx, int64_t n, int64_t m, int mode,
+                     int32_t *out_colors, int32_t *out_rounds);
+
+/*
+ * As ipgc_color_graph, with options (NULL: defaults), a HIP stream (a
+ * hipStream_t passed as void*; NULL: the null stream) on which all work is
+ * enqueued, and an optional per-round trace (NULL: none).  Still blocks until
+ * the result is complete, because out_rounds is host memory.
+ */
+int ipgc_color_graph_ex(const int32_t *csr_rowptr, const int32_t *csr_colidx, int64_t n, int64_t m, int mode,
+                        const ipgc_options *options, void *stream, int32_t *out_colors, int32_t *out_rounds,
+                        ipgc_trace *trace);
+
+/* Message for the last failing call on this thread ("" if none).  Valid until
+ * the next call on the same thread. */
+const char *ipgc_last_error(void);
+
+/* Name of profile kernel kind k ("" past the last kind). */
+const char *ipgc_kernel_name(int kind);
+
+/* ABI version: (major << 16) | minor. */
+int ipgc_version(void);
+
+/* Releases the cached per-device workspaces.  Optional; safe to call anytime
+ * no other call is in flight. */
+void ipgc_release_workspaces(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IPGC_H */

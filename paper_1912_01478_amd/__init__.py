@@ -1,0 +1,186 @@
+"""IPGC graph coloring on MI355X (gfx950): Python binding of the C-ABI library ``libipgc.so``.
+
+The method is Section II-C of Rai, M P, Pai, "A Hybrid Graph Coloring Algorithm for GPUs"
+(arXiv 1912.01478), run under the hybrid schedule of Section IV.  Every step of the coloring
+runs in the library's HIP kernels; this module only checks and marshals arguments.  PyTorch
+supplies device memory and streams.  There is no CPU fallback: if the library is missing the
+import of :func:`library` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libipgc.so")
+
+MODE_TOPOLOGY = 0
+MODE_DATA = 1
+MODE_HYBRID = 2
+MODES = {"topology": MODE_TOPOLOGY, "data": MODE_DATA, "hybrid": MODE_HYBRID}
+
+VALIDATE_DEFAULT = 0
+VALIDATE_NONE = 1
+VALIDATE_RANGES = 2
+
+STATUS = {0: "IPGC_OK", -1: "IPGC_EINVAL", -2: "IPGC_ETOOBIG", -3: "IPGC_EBADCSR", -4: "IPGC_ENOMEM",
+          -5: "IPGC_EHIP", -6: "IPGC_ELIMIT"}
+
+# Every symbol the header declares; the tests check that the library exports all of them.
+EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_last_error", "ipgc_kernel_name", "ipgc_version",
+           "ipgc_release_workspaces")
+PROFILE_KINDS = 16
+
+
+class IpgcError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("%s (%d): %s" % (STATUS.get(code, "?"), code, message))
+        self.code = code
+
+
+class Profile(ctypes.Structure):
+    """Mirror of ``ipgc_profile``."""
+    _fields_ = [("mask", ctypes.c_uint32), ("kinds", ctypes.c_int32),
+                ("ms", ctypes.c_double * PROFILE_KINDS), ("launches", ctypes.c_int64 * PROFILE_KINDS),
+                ("nodes", ctypes.c_int64 * PROFILE_KINDS), ("edges", ctypes.c_int64 * PROFILE_KINDS)]
+
+    def as_dict(self) -> dict:
+        out = {}
+        for k in range(self.kinds):
+            name = library().ipgc_kernel_name(k).decode()
+            out[name] = {"ms": self.ms[k], "launches": self.launches[k], "nodes": self.nodes[k],
+                         "edges": self.edges[k]}
+        return out
+
+
+class Options(ctypes.Structure):
+    """Mirror of ``ipgc_options``."""
+    _fields_ = [("threshold", ctypes.c_int64), ("light_max_degree", ctypes.c_int32),
+                ("wave_max_degree", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("profile", ctypes.POINTER(Profile))]
+
+
+class Trace(ctypes.Structure):
+    """Mirror of ``ipgc_trace``."""
+    _fields_ = [("capacity", ctypes.c_int64), ("wl_size", ctypes.POINTER(ctypes.c_int32)),
+                ("wl_degree", ctypes.POINTER(ctypes.c_int64)),
+                ("topology", ctypes.POINTER(ctypes.c_int8)), ("recorded", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load ``libipgc.so`` (built by ``build.py``); raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("HIP library %s is missing: run __graft_entry__.build() first" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+        lib.ipgc_color_graph.restype = i32
+        lib.ipgc_color_graph.argtypes = [vp, vp, i64, i64, i32, vp, ctypes.POINTER(ctypes.c_int32)]
+        lib.ipgc_color_graph_ex.restype = i32
+        lib.ipgc_color_graph_ex.argtypes = [vp, vp, i64, i64, i32, ctypes.POINTER(Options), vp, vp,
+                                            ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Trace)]
+        lib.ipgc_last_error.restype = ctypes.c_char_p
+        lib.ipgc_last_error.argtypes = []
+        lib.ipgc_kernel_name.restype = ctypes.c_char_p
+        lib.ipgc_kernel_name.argtypes = [i32]
+        lib.ipgc_version.restype = i32
+        lib.ipgc_version.argtypes = []
+        lib.ipgc_release_workspaces.restype = None
+        lib.ipgc_release_workspaces.argtypes = []
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise IpgcError(rc, library().ipgc_last_error().decode(errors="replace"))
+
+
+@dataclass
+class Coloring:
+    colors: "object"   # torch.int32 tensor on the device, 1-based colors
+    rounds: int
+    wl_sizes: list | None = None    # |WL_r| per round, when requested
+    wl_degrees: list | None = None  # degree sum over WL_r per round, when requested
+    topology: list | None = None    # 1 for topology-driven rounds, when requested
+    profile: dict | None = None     # per-kernel-kind event times and work units, when requested
+
+    @property
+    def num_colors(self) -> int:
+        return int(self.colors.max().item()) if self.colors.numel() else 0
+
+
+def _mode(mode) -> int:
+    if isinstance(mode, str):
+        return MODES[mode.lower()]
+    return int(mode)
+
+
+def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_degree: int = 0,
+                wave_max_degree: int = 0, validate: int = VALIDATE_DEFAULT, out=None, stream=None,
+                trace: bool = False, profile_mask: int = 0) -> Coloring:
+    """Color the symmetric CSR graph (``rowptr``: int32[n+1], ``colidx``: int32[m], both on the
+    HIP device) and return the 1-based colors and round count.  ``mode`` is "topology", "data"
+    or "hybrid"; ``threshold`` is H for hybrid rounds (0: floor(6n/10)).  Options only change
+    the time, never the result.  ``trace`` returns the per-round worklist sizes and degree sums;
+    ``profile_mask`` times the selected kernel kinds with HIP events (bit k = kind k)."""
+    import torch
+
+    if rowptr.dtype != torch.int32 or colidx.dtype != torch.int32:
+        raise TypeError("rowptr and colidx must be int32")
+    if not (rowptr.is_cuda and colidx.is_cuda):
+        raise ValueError("rowptr and colidx must be device tensors")
+    rowptr = rowptr.contiguous()
+    colidx = colidx.contiguous()
+    n = rowptr.numel() - 1
+    m = colidx.numel()
+    if n < 0:
+        raise ValueError("rowptr needs n+1 >= 1 entries")
+    if out is None:
+        out = torch.empty(n, dtype=torch.int32, device=rowptr.device)
+    elif out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() or out.device != rowptr.device:
+        raise ValueError("out must be a contiguous int32 tensor of n entries on the graph's device")
+    prof = Profile(int(profile_mask)) if profile_mask else None
+    opts = Options(int(threshold), int(light_max_degree), int(wave_max_degree), int(validate), 0,
+                   ctypes.pointer(prof) if prof is not None else None)
+    rounds = ctypes.c_int32(-1)
+    tr = None
+    if trace:
+        cap = max(n, 1)
+        wl = (ctypes.c_int32 * cap)()
+        wd = (ctypes.c_int64 * cap)()
+        topo = (ctypes.c_int8 * cap)()
+        tr = Trace(cap, ctypes.cast(wl, ctypes.POINTER(ctypes.c_int32)), ctypes.cast(wd, ctypes.POINTER(ctypes.c_int64)),
+                   ctypes.cast(topo, ctypes.POINTER(ctypes.c_int8)), 0)
+    if stream is None:
+        stream = torch.cuda.current_stream(rowptr.device)
+    with torch.cuda.device(rowptr.device):
+        rc = library().ipgc_color_graph_ex(
+            ctypes.c_void_p(rowptr.data_ptr()), ctypes.c_void_p(colidx.data_ptr() if m else 0), n, m,
+            _mode(mode), ctypes.byref(opts), ctypes.c_void_p(stream.cuda_stream),
+            ctypes.c_void_p(out.data_ptr() if n else 0), ctypes.byref(rounds),
+            ctypes.byref(tr) if tr is not None else None)
+    _check(rc)
+    res = Coloring(out, rounds.value)
+    if tr is not None:
+        k = tr.recorded
+        res.wl_sizes = list(wl[:k])
+        res.wl_degrees = list(wd[:k])
+        res.topology = list(topo[:k])
+    if prof is not None:
+        res.profile = prof.as_dict()
+    return res
+
+
+def color_graph_raw(rowptr_ptr: int, colidx_ptr: int, n: int, m: int, mode: int, out_ptr: int) -> int:
+    """The plain entry point ``ipgc_color_graph`` on raw device pointers; returns the round count."""
+    rounds = ctypes.c_int32(-1)
+    rc = library().ipgc_color_graph(ctypes.c_void_p(rowptr_ptr), ctypes.c_void_p(colidx_ptr), n, m, int(mode),
+                                    ctypes.c_void_p(out_ptr), ctypes.byref(rounds))
+    _check(rc)
+    return rounds.value

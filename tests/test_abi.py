@@ -1,0 +1,78 @@
+"""CPU checks of the C-ABI boundary: the built library loads, exports every function that
+include/ipgc.h declares, the Python mirrors of the structs match the header, and the product
+package does not reach the oracle."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ipgc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(ipgc_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1912_01478_amd as pkg
+    if not os.path.exists(pkg.LIB_PATH):
+        from paper_1912_01478_amd import build
+        build.build()
+    return pkg.library()
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    assert "ipgc_color_graph" in names and "ipgc_color_graph_ex" in names
+    import paper_1912_01478_amd as pkg
+    assert sorted(pkg.EXPORTS) == names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert getattr(lib, name) is not None
+
+
+def test_version(lib):
+    assert lib.ipgc_version() >> 16 == 1
+
+
+def test_struct_layouts():
+    import paper_1912_01478_amd as pkg
+    assert ctypes.sizeof(pkg.Options) == 32
+    assert ctypes.sizeof(pkg.Trace) == 40
+    assert ctypes.sizeof(pkg.Profile) == 8 + 8 * 16 * 4
+
+
+def test_kernel_names(lib):
+    names = []
+    k = 0
+    while lib.ipgc_kernel_name(k):
+        names.append(lib.ipgc_kernel_name(k).decode())
+        k += 1
+    assert len(names) >= 4 and len(set(names)) == len(names)
+    assert lib.ipgc_kernel_name(-1) == b"" and lib.ipgc_kernel_name(99) == b""
+
+
+def test_product_package_does_not_import_oracle():
+    pkg_dir = os.path.join(ROOT, "paper_1912_01478_amd")
+    for dirpath, _, files in os.walk(pkg_dir):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                for bad in ("import oracle", "from oracle", "ipgc_oracle", "libipgc_oracle"):
+                    assert bad not in src, (f, bad)
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    import paper_1912_01478_amd as pkg
+    monkeypatch.setattr(pkg, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(pkg, "_lib", None)
+    with pytest.raises(ImportError):
+        pkg.library()

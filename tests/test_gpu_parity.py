@@ -1,0 +1,216 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit (colors, round count and the
+per-round worklist sizes), for every schedule.  All comparisons are exact: the result is integer
+and the synchronous rules make it deterministic."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from tests import _props as P
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+MODES = ("topology", "data", "hybrid")
+
+
+def gpu(g, mode="hybrid", rowptr=None, colidx=None, **kw):
+    import paper_1912_01478_amd as ip
+    rowptr = g.rowptr if rowptr is None else rowptr
+    colidx = g.colidx if colidx is None else colidx
+    print("[gpu] %s n=%d m=%d mode=%s %s" % (g.name, g.n, g.m, mode, kw), flush=True)
+    rp = torch.from_numpy(np.ascontiguousarray(rowptr)).cuda()
+    ci = torch.from_numpy(np.ascontiguousarray(colidx)).cuda()
+    res = ip.color_graph(rp, ci, mode, trace=True, **kw)
+    torch.cuda.synchronize()
+    return res.colors.cpu().numpy(), res.rounds, np.asarray(res.wl_sizes, dtype=np.int64), res.topology
+
+
+def assert_parity(g, mode="hybrid", ref=None, **kw):
+    ref = ref or oracle.color_graph(g.rowptr, g.colidx)
+    col, rounds, wl, topo = gpu(g, mode, **kw)
+    assert rounds == ref.rounds, (rounds, ref.rounds)
+    bad = np.nonzero(col != ref.colors)[0]
+    assert bad.size == 0, "first mismatch at node %d: gpu %d oracle %d" % (bad[0], col[bad[0]], ref.colors[bad[0]])
+    assert (wl == ref.wl_sizes).all()
+    return col, rounds, wl, topo
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1912_01478_amd as ip
+    ip.library()
+
+
+# ------------------------------------------------------------------ closed forms and edge cases
+
+CLOSED = [gg.complete(1), gg.complete(2), gg.complete(40), gg.complete(300), gg.path(2), gg.path(101),
+          gg.cycle(8), gg.cycle(51), gg.star(5, 0), gg.star(70, 70), gg.star(3000, 0), gg.star(3000, 3000),
+          gg.complete_bipartite(5, 7), gg.complete_bipartite(40, 1500), gg.crown(9), gg.crown(40),
+          gg.empty(1), gg.empty(777)]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("g", CLOSED, ids=lambda g: g.name)
+def test_closed_forms(g, mode):
+    col, rounds, _, _ = assert_parity(g, mode)
+    P.check_coloring(g.rowptr, g.colidx, col, rounds)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_hand_traced_golden(mode):
+    from tests.test_oracle_pins import _read_hand_traced
+    for block in _read_hand_traced():
+        g = gg.from_edges(block["n"], block["edges"], name=block["name"])
+        col, rounds, wl, _ = gpu(g, mode)
+        assert col.tolist() == block["colors"] and rounds == block["rounds"][0] and wl.tolist() == block["wl"]
+
+
+def test_zero_nodes():
+    import paper_1912_01478_amd as ip
+    rp = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ci = torch.zeros(0, dtype=torch.int32, device="cuda")
+    res = ip.color_graph(rp, ci, "hybrid")
+    assert res.rounds == 0 and res.colors.numel() == 0
+
+
+def test_big_hub_and_clique_in_block_bucket():
+    """K_2100 puts every node in the workgroup bucket and needs 2100 colors (past one wave bitmap)."""
+    assert_parity(gg.complete(2100), "hybrid")
+    assert_parity(gg.star(200_000, 100_000), "data")
+
+
+# ------------------------------------------------------------------ random graphs, every schedule and option
+
+def small_graphs():
+    return [gg.config_graph(1),
+            gg.erdos_renyi(50_000, 24, gg.key(201, 0), name="er50k_d24"),
+            gg.config_graph(2, scale_down=8),   # R-MAT scale 14
+            gg.config_graph(2, scale_down=6),   # R-MAT scale 16, hubs near 10^4
+            gg.config_graph(3, scale_down=5),   # road, ~23k nodes
+            gg.road_knn(300_001, gg.key(202, 0), name="road300k")]
+
+
+SMALL = small_graphs()
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("g", SMALL, ids=lambda g: g.name)
+def test_random_parity(g, mode):
+    ref = oracle.color_graph(g.rowptr, g.colidx)
+    col, rounds, _, topo = assert_parity(g, mode, ref=ref)
+    expect_topo = {"topology": [1] * rounds, "data": [0] * rounds,
+                   "hybrid": [int(w > (6 * g.n) // 10) for w in ref.wl_sizes]}[mode]
+    assert topo == expect_topo
+
+
+@pytest.mark.parametrize("H", [1, 100, 5000, 10**9])
+@pytest.mark.parametrize("light,wave", [(1, 2), (8, 64), (32, 1024), (63, 2047)])
+def test_options_never_change_the_result(H, light, wave):
+    g = SMALL[3]
+    assert_parity(g, "hybrid", threshold=H, light_max_degree=light, wave_max_degree=wave)
+
+
+@pytest.mark.parametrize("g", SMALL[:4], ids=lambda g: g.name)
+def test_unsorted_rows(g):
+    """Row order is irrelevant; unsorted rows also switch off the sorted-row early exit."""
+    rp, ci = gg.shuffle_rows(g, 11)
+    assert_parity(g, "hybrid", rowptr=rp, colidx=ci)
+
+
+def test_no_validation_same_result():
+    import paper_1912_01478_amd as ip
+    assert_parity(SMALL[2], "hybrid", validate=ip.VALIDATE_NONE)
+
+
+def test_deterministic_across_runs():
+    g = SMALL[3]
+    a = gpu(g, "hybrid")
+    b = gpu(g, "hybrid")
+    assert (a[0] == b[0]).all() and a[1] == b[1] and (a[2] == b[2]).all()
+
+
+def test_plain_entry_point():
+    import paper_1912_01478_amd as ip
+    g = SMALL[0]
+    ref = oracle.color_graph(g.rowptr, g.colidx)
+    rp = torch.from_numpy(g.rowptr).cuda()
+    ci = torch.from_numpy(g.colidx).cuda()
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for mode in (ip.MODE_TOPOLOGY, ip.MODE_DATA, ip.MODE_HYBRID):
+        out.fill_(-7)
+        torch.cuda.synchronize()
+        rounds = ip.color_graph_raw(rp.data_ptr(), ci.data_ptr(), g.n, g.m, mode, out.data_ptr())
+        assert rounds == ref.rounds and (out.cpu().numpy() == ref.colors).all()
+
+
+# ------------------------------------------------------------------ errors
+
+def test_errors():
+    import paper_1912_01478_amd as ip
+    g = gg.path(5)
+    rp = torch.from_numpy(g.rowptr).cuda()
+    ci = torch.from_numpy(g.colidx).cuda()
+    with pytest.raises(ip.IpgcError) as e:
+        ip.color_graph(rp, ci, 7)
+    assert e.value.code == -1
+    bad = ci.clone()
+    bad[3] = 99
+    with pytest.raises(ip.IpgcError) as e:
+        ip.color_graph(rp, bad, "hybrid")
+    assert e.value.code == -3
+    bad = ci.clone()
+    bad[0] = -1
+    with pytest.raises(ip.IpgcError) as e:
+        ip.color_graph(rp, bad, "hybrid")
+    assert e.value.code == -3
+    rp2 = rp.clone()
+    rp2[0] = 1
+    with pytest.raises(ip.IpgcError) as e:
+        ip.color_graph(rp2, ci, "hybrid")
+    assert e.value.code == -3
+    rp3 = rp.clone()
+    rp3[2] = rp3[3] + 1  # decreasing row pointers
+    with pytest.raises(ip.IpgcError) as e:
+        ip.color_graph(rp3, ci, "hybrid")
+    assert e.value.code == -3
+    with pytest.raises(ip.IpgcError) as e:
+        ip.color_graph(rp, ci, "hybrid", light_max_degree=64)
+    assert e.value.code == -1
+    # the library still works after errors
+    assert_parity(g, "hybrid")
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+def _digests():
+    with open(os.path.join(GOLDEN, "oracle_digests.json")) as f:
+        return json.load(f)
+
+
+def _sha(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.int32).tobytes()).hexdigest()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_full_size_against_oracle_digest(cfg):
+    """Full-size workloads (G(10 000, 8); R-MAT scale 22 ef 16; road kNN on 24M points) against
+    digests of the oracle's colors and worklist trace written by golden/make_oracle_digests.py."""
+    d = _digests()[str(cfg)]
+    g = gg.config_graph(cfg)
+    assert g.digest() == d["graph_sha256"], "generator output changed"
+    for mode in MODES:
+        col, rounds, wl, _ = gpu(g, mode)
+        assert rounds == d["rounds"]
+        assert _sha(wl.astype(np.int32)) == d["wl_sizes_sha256"]
+        assert _sha(col) == d["colors_sha256"]
+    P.check_coloring(g.rowptr, g.colidx, col, rounds)
