@@ -26,17 +26,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
-# Algorithmic bytes per unit (active node / row entry of an active node) for each kernel kind.
-# Assign: worklist entry 4 + row bounds 8 + tentative write 4 per node; column index 4 + neighbour
-# color 4 per entry.  Conflict: worklist entry 4 + row bounds 8 + own tentative 4 + commit or push 4
-# per node; column index 4 + neighbour tentative 4 per entry.  Check: row bounds 8 per node and the
-# column index 4 per entry.  Init: row bounds 8 + color 4 + list entry 4 per node.
-UNIT_BYTES = {
-    "init": (16, 0), "check": (8, 4),
-    "assign_light": (16, 8), "assign_wave": (16, 8), "assign_block": (16, 8),
-    "conflict_light": (20, 8), "conflict_wave": (20, 8), "conflict_block": (20, 8),
-    "round_end": (0, 0),
-}
+# Algorithmic bytes per work unit counted on the device ("Measurement").
+#   assign_nodes      worklist entry (or state read of a sweep) 4 + row bounds 8 + state write 4
+#   pull_entries      column index 4 + neighbour state 4           (thread-per-node assign)
+#   map_bytes         one byte-map byte read                       (first free color of W/M nodes)
+#   conflict_nodes    list entry 4 + bounds 8 + own state 4 + commit or worklist push 4
+#   conflict_entries  list entry 4 + neighbour state 4
+#   list_writes       one kept list entry written back 4
+#   push_entries      column index 4 + neighbour byte-map metadata 8 + byte store 1
+UNIT_BYTES = {"assign_nodes": 16, "pull_entries": 8, "map_bytes": 1, "conflict_nodes": 20,
+              "conflict_entries": 8, "list_writes": 4, "push_entries": 13, "commits": 0}
 
 
 def log(*a):
@@ -115,22 +114,23 @@ def main():
 
     # per-kernel profile and trace of one more (untimed) call
     prof = pkg.color_graph(rp, ci, args.mode, out=out, trace=True, profile_mask=0xFFFF)
+    units = prof.profile["units"]
+    alg_round_bytes = sum(UNIT_BYTES.get(k, 0) * v for k, v in units.items())
     kinds = {}
-    for name, p in prof.profile.items():
+    for name, p in prof.profile["kernels"].items():
         if p["launches"] == 0:
             continue
-        nb, eb = UNIT_BYTES.get(name, (0, 0))
-        alg = nb * p["nodes"] + eb * p["edges"]
-        kinds[name] = {"ms": round(p["ms"], 4), "launches": p["launches"], "avg_us": round(1000 * p["ms"] / p["launches"], 2),
-                       "alg_bytes": alg, "alg_GBps": round(alg / (p["ms"] * 1e6), 1) if p["ms"] > 0 else None}
+        kinds[name] = {"ms": round(p["ms"], 4), "launches": p["launches"], "avg_us": round(1000 * p["ms"] / p["launches"], 2)}
     dom = max(kinds, key=lambda k: kinds[k]["ms"])
-    d = kinds[dom]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(d["alg_GBps"] / HBM_PEAK_GBPS, 4) if d["alg_GBps"] else None, "traffic": None,
-                "avg_launch_us": d["avg_us"], "launches": d["launches"]}
+    kd = kinds[dom]
+    alg = alg_round_bytes / kd["launches"] if dom in ("rounds",) else None
+    achieved = round(alg / (kd["avg_us"] * 1e3), 1) if alg else None
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None, "traffic": None,
+                "alg_bytes_per_launch": alg, "avg_launch_us": kd["avg_us"], "launches": kd["launches"]}
     wl = np.asarray(prof.wl_sizes, dtype=np.int64)
     wd = np.asarray(prof.wl_degrees, dtype=np.int64)
-    path_bytes = int(36 * wl.sum() + 16 * wd.sum())
+    pull_model_bytes = int(36 * wl.sum() + 16 * wd.sum())
 
     modes = {args.mode: {"ms_per_step": round(ms, 3), "edges_per_s": g.m / (ms / 1000.0)}}
     if args.compare_steps > 0:
@@ -169,8 +169,8 @@ def main():
         "hybrid_speedup_vs_data": round(modes["data"]["ms_per_step"] / modes["hybrid"]["ms_per_step"], 3)
         if "data" in modes and "hybrid" in modes else None,
         "roofline": roofline,
-        "path_alg_bytes": path_bytes,
-        "path_alg_GBps": round(path_bytes / (ms * 1e6), 1),
+        "work_units": units,
+        "pull_model_bytes": pull_model_bytes,
         "kernels": kinds,
         "cpu_baseline": cpu,
     }

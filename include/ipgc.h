@@ -70,22 +70,30 @@ enum {
     IPGC_VALIDATE_RANGES = 2   /* also rowptr non-decreasing and every column id in [0, n) */
 };
 
-/* Kernel kinds that ipgc_profile can time (see ipgc_kernel_name). */
+/* Kernel kinds that ipgc_profile can time (see ipgc_kernel_name) and work
+ * unit kinds it reports (see ipgc_unit_name). */
 #define IPGC_PROFILE_KINDS 16
 
 /* Optional device-time profile of one call.  Kernel kinds whose bit is set in
- * `mask` are bracketed by HIP events recorded on the call's stream; the event
- * times, launch counts and the work units each kind processed are summed here.
- * Work units: `nodes` = active nodes handled (a topology sweep's inactive nodes
- * are not counted), `edges` = row entries of those nodes (their degree sum).
- * Host memory owned by the caller; the out fields are overwritten. */
+ * `mask` are bracketed by HIP events recorded on the call's stream; event
+ * times and launch counts are summed per kind.  `units` are work counts the
+ * kernels keep on the device (active nodes handled, neighbour entries read,
+ * ...), from which an algorithmic byte count follows.  Host memory owned by
+ * the caller; every out field is overwritten. */
 typedef struct ipgc_profile {
     uint32_t mask;                            /* in: bit k times kernel kind k */
-    int32_t kinds;                            /* out: number of kinds defined */
+    int32_t kinds;                            /* out: number of kernel kinds defined */
     double ms[IPGC_PROFILE_KINDS];            /* out: summed event time per kind */
     int64_t launches[IPGC_PROFILE_KINDS];     /* out: timed launches per kind */
-    int64_t nodes[IPGC_PROFILE_KINDS];        /* out: active nodes processed per kind (all launches) */
-    int64_t edges[IPGC_PROFILE_KINDS];        /* out: row entries of those nodes per kind */
+    int32_t unit_kinds;                       /* out: number of work unit kinds defined */
+    int32_t reserved;
+    int64_t units[IPGC_PROFILE_KINDS];        /* out: work units of the whole call */
+    uint64_t *phase_ticks;                    /* in: host array or NULL.  out: device wall-clock ticks at
+                                                 the start of each round's assign and conflict steps
+                                                 (3 per round: assign, conflict, hub push) and at the end */
+    int64_t phase_capacity;                   /* in: entries available in phase_ticks */
+    int64_t phase_recorded;                   /* out: entries written */
+    int64_t tick_khz;                         /* out: rate of the tick counter */
 } ipgc_profile;
 
 /* Tuning options.  A zeroed struct (or NULL) selects every default.  No option
@@ -93,13 +101,21 @@ typedef struct ipgc_profile {
 typedef struct ipgc_options {
     int64_t threshold;         /* H for HYBRID (topology round iff |WL| > H); 0 or less: floor(6n/10), the
                                   paper's 60% of the node count.  Ignored by TOPOLOGY and DATA. */
-    int32_t light_max_degree;  /* nodes with degree <= this run thread-per-node (1..63; 0: default 32) */
-    int32_t wave_max_degree;   /* nodes with degree <= this run wavefront-per-node; larger ones run
-                                  workgroup-per-node (light_max_degree+1 .. 2047; 0: default 1024) */
+    int32_t light_max_degree;  /* nodes with degree <= this run a thread each and read their
+                                  neighbours' colors every round (1..32; 0: default 32) */
+    int32_t hub_min_degree;    /* nodes with degree above this are hubs: their conflict scans run a
+                                  workgroup each, and neighbours read hub colors instead of hubs
+                                  writing them out (> light_max_degree; 0: default 4096) */
     int32_t validate;          /* IPGC_VALIDATE_* */
-    int32_t reserved;          /* must be 0 */
-    ipgc_profile *profile;     /* optional per-kernel timing (NULL: none) */
+    int32_t flags;             /* IPGC_FLAG_* */
+    ipgc_profile *profile;     /* optional per-kernel timing and work counts (NULL: none) */
 } ipgc_options;
+
+/* Option flags. */
+enum {
+    IPGC_FLAG_STEPPED = 1      /* one launch per round step instead of one cooperative launch for all
+                                  rounds (same result; used for per-step timing) */
+};
 
 /* Per-round record, filled on request.  Host memory owned by the caller. */
 typedef struct ipgc_trace {
@@ -145,6 +161,9 @@ const char *ipgc_last_error(void);
 
 /* Name of profile kernel kind k ("" past the last kind). */
 const char *ipgc_kernel_name(int kind);
+
+/* Name of profile work unit kind k ("" past the last kind). */
+const char *ipgc_unit_name(int kind);
 
 /* ABI version: (major << 16) | minor. */
 int ipgc_version(void);

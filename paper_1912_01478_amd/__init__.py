@@ -28,8 +28,9 @@ STATUS = {0: "IPGC_OK", -1: "IPGC_EINVAL", -2: "IPGC_ETOOBIG", -3: "IPGC_EBADCSR
           -5: "IPGC_EHIP", -6: "IPGC_ELIMIT"}
 
 # Every symbol the header declares; the tests check that the library exports all of them.
-EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_last_error", "ipgc_kernel_name", "ipgc_version",
-           "ipgc_release_workspaces")
+EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_last_error", "ipgc_kernel_name", "ipgc_unit_name",
+           "ipgc_version", "ipgc_release_workspaces")
+FLAG_STEPPED = 1
 PROFILE_KINDS = 16
 
 
@@ -43,22 +44,28 @@ class Profile(ctypes.Structure):
     """Mirror of ``ipgc_profile``."""
     _fields_ = [("mask", ctypes.c_uint32), ("kinds", ctypes.c_int32),
                 ("ms", ctypes.c_double * PROFILE_KINDS), ("launches", ctypes.c_int64 * PROFILE_KINDS),
-                ("nodes", ctypes.c_int64 * PROFILE_KINDS), ("edges", ctypes.c_int64 * PROFILE_KINDS)]
+                ("unit_kinds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("units", ctypes.c_int64 * PROFILE_KINDS), ("phase_ticks", ctypes.POINTER(ctypes.c_uint64)),
+                ("phase_capacity", ctypes.c_int64), ("phase_recorded", ctypes.c_int64),
+                ("tick_khz", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
-        out = {}
-        for k in range(self.kinds):
-            name = library().ipgc_kernel_name(k).decode()
-            out[name] = {"ms": self.ms[k], "launches": self.launches[k], "nodes": self.nodes[k],
-                         "edges": self.edges[k]}
+        lib = library()
+        kernels = {lib.ipgc_kernel_name(k).decode(): {"ms": self.ms[k], "launches": self.launches[k]}
+                   for k in range(self.kinds)}
+        units = {lib.ipgc_unit_name(k).decode(): self.units[k] for k in range(self.unit_kinds)}
+        out = {"kernels": kernels, "units": units}
+        if self.phase_recorded:
+            out["phase_ticks"] = [self.phase_ticks[i] for i in range(self.phase_recorded)]
+            out["tick_khz"] = self.tick_khz
         return out
 
 
 class Options(ctypes.Structure):
     """Mirror of ``ipgc_options``."""
     _fields_ = [("threshold", ctypes.c_int64), ("light_max_degree", ctypes.c_int32),
-                ("wave_max_degree", ctypes.c_int32), ("validate", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("profile", ctypes.POINTER(Profile))]
+                ("hub_min_degree", ctypes.c_int32), ("validate", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("profile", ctypes.POINTER(Profile))]
 
 
 class Trace(ctypes.Structure):
@@ -88,6 +95,8 @@ def library() -> ctypes.CDLL:
         lib.ipgc_last_error.argtypes = []
         lib.ipgc_kernel_name.restype = ctypes.c_char_p
         lib.ipgc_kernel_name.argtypes = [i32]
+        lib.ipgc_unit_name.restype = ctypes.c_char_p
+        lib.ipgc_unit_name.argtypes = [i32]
         lib.ipgc_version.restype = i32
         lib.ipgc_version.argtypes = []
         lib.ipgc_release_workspaces.restype = None
@@ -122,13 +131,15 @@ def _mode(mode) -> int:
 
 
 def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_degree: int = 0,
-                wave_max_degree: int = 0, validate: int = VALIDATE_DEFAULT, out=None, stream=None,
-                trace: bool = False, profile_mask: int = 0) -> Coloring:
+                hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT, stepped: bool = False, out=None,
+                stream=None, trace: bool = False, profile_mask: int = 0, timeline: int = 0) -> Coloring:
     """Color the symmetric CSR graph (``rowptr``: int32[n+1], ``colidx``: int32[m], both on the
     HIP device) and return the 1-based colors and round count.  ``mode`` is "topology", "data"
-    or "hybrid"; ``threshold`` is H for hybrid rounds (0: floor(6n/10)).  Options only change
-    the time, never the result.  ``trace`` returns the per-round worklist sizes and degree sums;
-    ``profile_mask`` times the selected kernel kinds with HIP events (bit k = kind k)."""
+    or "hybrid"; ``threshold`` is H for hybrid rounds (0: floor(6n/10)).  ``stepped`` runs one
+    launch per round step instead of one cooperative launch.  Options only change the time,
+    never the result.  ``trace`` returns the per-round worklist sizes and degree sums;
+    ``profile_mask`` times the selected kernel kinds with HIP events (bit k = kind k); ``timeline``
+    > 0 records that many device wall-clock ticks at the round-step boundaries."""
     import torch
 
     if rowptr.dtype != torch.int32 or colidx.dtype != torch.int32:
@@ -145,9 +156,15 @@ def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_
         out = torch.empty(n, dtype=torch.int32, device=rowptr.device)
     elif out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() or out.device != rowptr.device:
         raise ValueError("out must be a contiguous int32 tensor of n entries on the graph's device")
-    prof = Profile(int(profile_mask)) if profile_mask else None
-    opts = Options(int(threshold), int(light_max_degree), int(wave_max_degree), int(validate), 0,
-                   ctypes.pointer(prof) if prof is not None else None)
+    prof = None
+    if profile_mask or timeline:
+        prof = Profile(int(profile_mask))
+        if timeline:
+            ticks = (ctypes.c_uint64 * int(timeline))()
+            prof.phase_ticks = ctypes.cast(ticks, ctypes.POINTER(ctypes.c_uint64))
+            prof.phase_capacity = int(timeline)
+    opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), int(validate),
+                   FLAG_STEPPED if stepped else 0, ctypes.pointer(prof) if prof is not None else None)
     rounds = ctypes.c_int32(-1)
     tr = None
     if trace:

@@ -1,0 +1,875 @@
+// Device code of the IPGC library: data layout, helpers, preparation kernels,
+// the two per-round steps of IPGC (Section II-C of Rai, M P, Pai, "A Hybrid
+// Graph Coloring Algorithm for GPUs", arXiv 1912.01478) and the round schedule
+// of Section IV (a topology-driven sweep or a data-driven worklist pass, picked
+// per round from the worklist size; the worklist is kept in both).
+//
+// Color state: one int32 per node in the caller's output buffer.
+//   c[v] > 0   v holds committed color c[v];
+//   c[v] <= 0  v is uncolored; after the assign step it holds -t (t >= 1 is its
+//              tentative color of the round).
+// Assign reads only c[u] > 0, so concurrent writes of -t are invisible to it.
+// Conflict compares |c[u]| with the node's own tentative color: a neighbour
+// that commits in the same step flips -t to +t, |c[u]| unchanged, and a
+// neighbour committed in an earlier round holds a color that was forbidden to
+// the node, so it never matches.  The result is the synchronous one whatever
+// the timing, with no second state array.
+//
+// Node classes by degree d:
+//   L (d <= light_max <= 32)  a thread per node.  Assign reads the row's colors
+//                             into a 64-bit mask (the answer is at most d+1);
+//                             conflict scans the row.
+//   W (light_max < d <= hub)  a wavefront per node.  Forbidden colors live in a
+//                             byte map F_v (one byte per color 1..d+1) that
+//                             committing neighbours write into; assign scans
+//                             F_v from the node's previous tentative color (the
+//                             first free color never decreases, because
+//                             committed colors never change).
+//   M (d > hub)               as W, except that when an M node commits, the
+//                             whole grid writes its color into its neighbours'
+//                             byte maps in a separate step of the round (a
+//                             hub's row is too long for one wavefront).
+// Conflict scans of W/M nodes read a private list of the node's smaller
+// neighbours (u < v) kept in a ring inside the node's CSR-sized region: each
+// scan drops the neighbours it finds committed and moves the start past what
+// it read, so every dead entry is read once after it dies and the scan
+// position rotates through the list.
+//
+// Worklists are split into one segment per workgroup and class; a workgroup
+// appends its losers to its own segments with shared-memory counters, so no
+// global atomic is involved.  Readers map item numbers to segments with a
+// prefix sum of the segment counts held in shared memory.
+//
+// Grid barrier (cooperative launch): workgroups run on the XCD given by their
+// XCC_ID register.  The last workgroup of an XCD to arrive writes back that
+// XCD's L2 (agent-scope release) once for all of them; the XCD leaders meet on
+// a global counter; every workgroup then invalidates its caches (agent-scope
+// acquire).  Before arriving, every thread waits until its stores have reached
+// the L2, which all workgroups of the XCD share.
+#pragma once
+
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ipgc {
+
+constexpr int kWave = 64;
+constexpr int kPrepBlock = 256;
+constexpr int kRoundBlock = 1024;        // 16 wavefronts; one workgroup per CU
+constexpr int kRoundWaves = kRoundBlock / kWave;
+constexpr int kMaxRoundBlocks = 1024;    // cap on the cooperative grid
+constexpr int kLightMaxLimit = 32;       // thread-per-node pull uses a 64-bit mask: d + 1 <= 64
+constexpr int kMaxXcc = 16;
+
+enum { kL = 0, kW = 1, kM = 2, kNumClasses = 3 };
+
+// Work counters (units for the algorithmic byte count).
+enum {
+    kUAssignNodes = 0,  // nodes given a tentative color
+    kUPullEntries,      // row entries read by thread-per-node assigns
+    kUMapBytes,         // byte-map bytes scanned by W/M assigns
+    kUConflictNodes,    // nodes tested for conflicts
+    kUConflictEntries,  // neighbour entries read by conflict scans
+    kUListWrites,       // list entries kept and rewritten by W/M conflict scans
+    kUPushEntries,      // row entries read by winners writing into neighbours' byte maps
+    kUCommits,          // nodes committed
+    kNumUnits
+};
+
+struct alignas(128) Line {
+    unsigned v;
+    unsigned pad[31];
+};
+
+struct Barrier {
+    Line xcnt[kMaxXcc];   // arrivals per XCD
+    Line xsize[kMaxXcc];  // workgroups per XCD
+    Line gcnt;            // XCD leaders arrived
+    Line gen;             // global generation
+    Line xgen[kMaxXcc];   // generation released per XCD
+    Line setup;           // one-time flat barrier counter
+};
+
+// Scalars shared by every kernel of a call.
+struct Counters {
+    int64_t class_deg[kNumClasses];   // degree sum per class (static list)
+    int64_t unit_nodes[4];            // active nodes per class summed over rounds
+    int64_t unit_edges[4];            // their degree sums summed over rounds
+    int32_t class_n[kNumClasses];     // nodes per class
+    int32_t static_off[4];            // class regions of the static list
+    int32_t seg_off[4];               // class regions of the segmented lists
+    int32_t seg_cap[kNumClasses];     // entries per workgroup segment, per class
+    int32_t finished;
+    int32_t rounds;
+    int32_t bad_rows;
+    int32_t bad_ids;
+    int32_t unsorted;
+    int32_t hub_winners;              // hubs committed in the current round
+    int32_t pad[2];
+};
+
+struct Dev {
+    const int32_t *rowptr;
+    const int32_t *colidx;
+    int32_t *c;              // color state (caller's output)
+    const int8_t *cls;       // class per node
+    const uint2 *fmeta;      // {byte-map base, byte-map size = d+1} per node; size 0 for class L
+    uint8_t *F;              // byte maps
+    int32_t *lower;          // ring of smaller neighbours per W/M node (region rowptr[v] .. + d)
+    int32_t *lstart;         // ring start per node
+    int32_t *llen;           // ring length per node
+    int32_t *static_list;    // every node grouped by class (ascending id inside a class)
+    int32_t *seg_list[2];    // the two alternating segmented worklists
+    int32_t *seg_cnt[2];     // [kNumClasses][grid] entries per segment
+    int64_t *seg_deg[2];     // [kNumClasses][grid] degree sum per segment
+    int32_t *hub_won;        // hubs committed in the current round
+    int32_t *block_cnt;      // [kNumClasses][prep grid] class counts per preparation workgroup
+    int64_t *block_deg;      // [kNumClasses][prep grid]
+    int64_t *units;          // [kNumUnits][grid] work counters per round workgroup
+    Counters *ct;
+    Barrier *bar;
+    int32_t *trace;          // |WL_r| per round
+    int64_t *trace_deg;      // degree sum over WL_r per round
+    int64_t trace_cap;
+    uint64_t *ticks;         // optional timeline: wall clock at each step start
+    int64_t tick_cap;
+    int64_t threshold;       // topology round iff |WL| > threshold
+    int32_t n;
+    int32_t m;
+    int32_t light_max;
+    int32_t hub_min;         // degree above which a node is class M
+    int32_t sorted;          // every row strictly ascending
+    int32_t grid;            // workgroups of the round kernels (segments per class)
+};
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanes_below() {
+    const int l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ int64_t wave_sum(int64_t x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+__device__ __forceinline__ int32_t iabs(int32_t x) { return x < 0 ? -x : x; }
+
+__device__ __forceinline__ int node_class(int64_t d, int light_max, int hub_min) {
+    return d <= light_max ? kL : (d <= hub_min ? kW : kM);
+}
+
+__device__ __forceinline__ unsigned ld_agent(unsigned *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(unsigned *p, unsigned v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned add_agent(unsigned *p, unsigned v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned xcc_id() {
+    // XCC_ID hardware register (id 20), bits [3:0]
+    return (unsigned)__builtin_amdgcn_s_getreg(20 | (0 << 6) | (3 << 11)) & (kMaxXcc - 1);
+}
+
+// ============================================================== grid barrier
+
+struct GridBarrier {
+    Barrier *b;
+    unsigned xcc, nxcc, gen;
+
+    // One-time setup: count the workgroups of every XCD (flat barrier with a
+    // per-workgroup release and acquire; used once per launch).
+    __device__ void setup(Barrier *bar) {
+        b = bar;
+        xcc = xcc_id();
+        if (threadIdx.x == 0) {
+            add_agent(&b->xsize[xcc].v, 1u);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            add_agent(&b->setup.v, 1u);
+            while (ld_agent(&b->setup.v) < gridDim.x) __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        nxcc = 0;
+        for (int i = 0; i < kMaxXcc; ++i) nxcc += ld_agent(&b->xsize[i].v) > 0;
+        gen = 0;
+    }
+
+    __device__ void sync() {
+        __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have reached the XCD's L2
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const unsigned g = gen;
+            const unsigned xs = ld_agent(&b->xsize[xcc].v);
+            if (add_agent(&b->xcnt[xcc].v, 1u) == xs - 1) {
+                st_agent(&b->xcnt[xcc].v, 0u);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // write back this XCD's L2
+                if (add_agent(&b->gcnt.v, 1u) == nxcc - 1) {
+                    st_agent(&b->gcnt.v, 0u);
+                    st_agent(&b->gen.v, g + 1);
+                } else {
+                    while (ld_agent(&b->gen.v) == g) __builtin_amdgcn_s_sleep(1);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                st_agent(&b->xgen[xcc].v, g + 1);
+            } else {
+                while (ld_agent(&b->xgen[xcc].v) == g) __builtin_amdgcn_s_sleep(1);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+        }
+        gen += 1;
+        __syncthreads();
+    }
+};
+
+// ============================================================== preparation
+
+// Block-wide exclusive scan of one int per thread (any block size <= 1024).
+__device__ __forceinline__ int block_scan(int x, int *total) {
+    __shared__ int s_wave[32];
+    const int lane = lane_id(), w = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
+    int incl = x;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) s_wave[w] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int i = 0; i < nw; ++i) {
+            const int t = s_wave[i];
+            s_wave[i] = acc;
+            acc += t;
+        }
+        s_wave[31] = acc;
+    }
+    __syncthreads();
+    const int excl = s_wave[w] + incl - x;
+    *total = s_wave[31];
+    __syncthreads();
+    return excl;
+}
+
+// Initial state (Section II-C: every node starts uncolored, every node is in
+// the worklist), classes, byte-map metadata, row-pointer checks, and the class
+// counts of each workgroup's node range.  Workgroup b covers nodes
+// [b*span, (b+1)*span).
+__global__ __launch_bounds__(kPrepBlock) void k_init(Dev d, int8_t *cls, uint2 *fmeta, int32_t span) {
+    const int64_t lo = (int64_t)blockIdx.x * span, hi = std::min<int64_t>(lo + span, d.n);
+    int cnt[kNumClasses] = {0, 0, 0};
+    int64_t deg[kNumClasses] = {0, 0, 0};
+    int bad = 0;
+    for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+        d.c[v] = 0;
+        const int32_t a = d.rowptr[v], e = d.rowptr[v + 1];
+        const bool b = a < 0 || e < a || e > d.m;
+        bad |= b;
+        const int64_t dv = b ? 0 : e - a;
+        const int k = node_class(dv, d.light_max, d.hub_min);
+        cls[v] = (int8_t)k;
+        fmeta[v] = k == kL ? make_uint2(0u, 0u) : make_uint2((uint32_t)a + (uint32_t)v, (uint32_t)dv + 1u);
+        cnt[k] += 1;
+        deg[k] += dv;
+    }
+    if (__ballot(bad) && lane_id() == 0) d.ct->bad_rows = 1;
+    __shared__ int s_cnt[kNumClasses];
+    __shared__ unsigned long long s_deg[kNumClasses];
+    if (threadIdx.x < kNumClasses) {
+        s_cnt[threadIdx.x] = 0;
+        s_deg[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (int k = 0; k < kNumClasses; ++k) {
+        const int64_t ds = wave_sum(deg[k]);
+        const int64_t cs = wave_sum(cnt[k]);
+        if (lane_id() == 0) {
+            atomicAdd(&s_cnt[k], (int)cs);
+            atomicAdd(&s_deg[k], (unsigned long long)ds);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumClasses) {
+        d.block_cnt[threadIdx.x * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
+        d.block_deg[threadIdx.x * gridDim.x + blockIdx.x] = (int64_t)s_deg[threadIdx.x];
+    }
+}
+
+// Prefix of the per-workgroup class counts (one workgroup): static-list
+// offsets per preparation workgroup, class sizes and regions, segment sizes.
+__global__ __launch_bounds__(1024) void k_offsets(Dev d, int32_t prep_grid) {
+    int32_t base = 0;
+    for (int k = 0; k < kNumClasses; ++k) {
+        int64_t dsum = 0;
+        for (int32_t b0 = 0; b0 < prep_grid; b0 += blockDim.x) {
+            const int32_t b = b0 + threadIdx.x;
+            const int x = b < prep_grid ? d.block_cnt[k * prep_grid + b] : 0;
+            int tot;
+            const int ex = block_scan(x, &tot);
+            if (b < prep_grid) d.block_cnt[k * prep_grid + b] = base + ex;
+            base += tot;
+            const int64_t ds = b < prep_grid ? d.block_deg[k * prep_grid + b] : 0;
+            dsum += wave_sum(ds);  // lane 0 of each wave holds its part
+        }
+        __shared__ unsigned long long s_d;
+        if (threadIdx.x == 0) s_d = 0;
+        __syncthreads();
+        if (lane_id() == 0) atomicAdd(&s_d, (unsigned long long)dsum);
+        __syncthreads();
+        if (threadIdx.x == 0) d.ct->class_deg[k] = (int64_t)s_d;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        // block_cnt now holds exclusive offsets; class boundaries from the last workgroup's offsets
+        int32_t off[kNumClasses + 1];
+        off[0] = 0;
+        for (int k = 1; k < kNumClasses; ++k) off[k] = d.block_cnt[k * prep_grid];
+        off[kNumClasses] = d.n;
+        int32_t so = 0;
+        for (int k = 0; k < kNumClasses; ++k) {
+            d.ct->static_off[k] = off[k];
+            d.ct->class_n[k] = off[k + 1] - off[k];
+            const int32_t cap = (d.ct->class_n[k] + d.grid - 1) / d.grid + kRoundBlock;
+            d.ct->seg_cap[k] = cap;
+            d.ct->seg_off[k] = so;
+            so += cap * d.grid;
+        }
+        d.ct->static_off[kNumClasses] = d.n;
+        d.ct->seg_off[kNumClasses] = so;
+    }
+}
+
+// The static list: every node grouped by class, ascending id within a class.
+__global__ __launch_bounds__(kPrepBlock) void k_fill_static(Dev d, int32_t span) {
+    const int64_t lo = (int64_t)blockIdx.x * span, hi = std::min<int64_t>(lo + span, d.n);
+    int32_t base[kNumClasses];
+    for (int k = 0; k < kNumClasses; ++k) base[k] = d.block_cnt[k * gridDim.x + blockIdx.x];
+    for (int64_t v0 = lo; v0 < hi; v0 += blockDim.x) {
+        const int64_t v = v0 + threadIdx.x;
+        const int k = v < hi ? d.cls[v] : -1;
+        for (int q = 0; q < kNumClasses; ++q) {
+            int tot;
+            const int ex = block_scan(k == q, &tot);
+            if (k == q) d.static_list[base[q] + ex] = (int32_t)v;
+            base[q] += tot;
+        }
+    }
+}
+
+// Column checks: ids inside [0, n) and strictly ascending rows.  Light rows a
+// thread each, wider rows a wavefront each.
+__global__ __launch_bounds__(kPrepBlock) void k_check(Dev d) {
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gw = gt / kWave, nw = nt / kWave;
+    const int lane = lane_id();
+    int bad = 0, unsorted = 0;
+    const int32_t nL = d.ct->class_n[kL];
+    const int32_t *listL = d.static_list + d.ct->static_off[kL];
+    for (int64_t i = gt; i < nL; i += nt) {
+        const int32_t v = listL[i];
+        int32_t prev = -1;
+        for (int32_t k = d.rowptr[v]; k < d.rowptr[v + 1]; ++k) {
+            const int32_t u = d.colidx[k];
+            bad |= (u < 0 || u >= d.n);
+            unsorted |= (u <= prev);
+            prev = u;
+        }
+    }
+    const int32_t nWide = d.ct->class_n[kW] + d.ct->class_n[kM];
+    const int32_t *listWide = d.static_list + d.ct->static_off[kW];
+    for (int64_t i = gw; i < nWide; i += nw) {
+        const int32_t v = listWide[i];
+        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1];
+        for (int32_t k = b + lane; k < e; k += kWave) {
+            const int32_t u = d.colidx[k];
+            bad |= (u < 0 || u >= d.n);
+            if (k + 1 < e) unsorted |= (d.colidx[k + 1] <= u);
+        }
+    }
+    if (__ballot(bad) && lane == 0) d.ct->bad_ids = 1;
+    if (__ballot(unsorted) && lane == 0) d.ct->unsorted = 1;
+}
+
+// Per W/M node (a wavefront each): clear its byte map and copy its smaller
+// neighbours into its ring, neighbours of class W or M first.
+__global__ __launch_bounds__(kPrepBlock) void k_prep_wide(Dev d) {
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int lane = lane_id();
+    const int32_t nWide = d.ct->class_n[kW] + d.ct->class_n[kM];
+    const int32_t *listWide = d.static_list + d.ct->static_off[kW];
+    for (int64_t i = gw; i < nWide; i += nw) {
+        const int32_t v = listWide[i];
+        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1];
+        const uint2 fm = d.fmeta[v];
+        for (uint32_t k = lane; k < fm.y; k += kWave) d.F[(uint64_t)fm.x + k] = 0;
+        int32_t nwide = 0;
+        for (int32_t k0 = b; k0 < e; k0 += kWave) {
+            const int32_t k = k0 + lane;
+            const bool first = k < e && d.colidx[k] < v && d.cls[d.colidx[k]] != kL;
+            nwide += __popcll(__ballot(first));
+        }
+        int32_t pos_wide = 0, pos_light = nwide;
+        for (int32_t k0 = b; k0 < e; k0 += kWave) {
+            const int32_t k = k0 + lane;
+            int32_t u = -1;
+            int q = -1;
+            if (k < e) {
+                u = d.colidx[k];
+                if (u < v) q = d.cls[u] != kL ? 0 : 1;
+            }
+            const uint64_t m0 = __ballot(q == 0), m1 = __ballot(q == 1);
+            if (q == 0) d.lower[b + pos_wide + __popcll(m0 & lanes_below())] = u;
+            if (q == 1) d.lower[b + pos_light + __popcll(m1 & lanes_below())] = u;
+            pos_wide += __popcll(m0);
+            pos_light += __popcll(m1);
+        }
+        if (lane == 0) {
+            d.lstart[v] = 0;
+            d.llen[v] = pos_light;
+        }
+    }
+}
+
+// ============================================================== worklist views
+
+// The items of one class in the round's input: either the static list (a
+// topology-driven sweep, or round 1) or the segmented list of the previous
+// round, read through the prefix sums of its segment counts.
+struct ClassView {
+    const int32_t *base;  // static: first entry of the class; segmented: first segment of the class
+    const int32_t *pre;   // segmented: shared-memory prefix sums (grid + 1 entries), else null
+    int32_t cap;          // segmented: entries per segment
+    int32_t total;
+
+    __device__ __forceinline__ int32_t at(int32_t i) const {
+        if (!pre) return base[i];
+        // the segment s with pre[s] <= i < pre[s+1]
+        int lo = 0, hi = gridDim.x;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        return base[(int64_t)lo * cap + (i - pre[lo])];
+    }
+};
+
+struct RoundIn {
+    ClassView cv[kNumClasses];
+    int32_t wl[kNumClasses];  // worklist entries per class (the active nodes)
+    int32_t total;            // worklist size |WL_r|
+    bool topo;
+};
+
+// Load the segment counts of list `src` and build the prefix sums in shared
+// memory (all threads of the workgroup call this).
+__device__ void load_segments(const Dev &d, int src, int32_t (*pre)[kMaxRoundBlocks + 1]) {
+    const int nb = gridDim.x;
+    for (int k = 0; k < kNumClasses; ++k) {
+        const int32_t x = threadIdx.x < (unsigned)nb ? d.seg_cnt[src][k * nb + threadIdx.x] : 0;
+        int tot;
+        const int ex = block_scan(x, &tot);
+        if (threadIdx.x < (unsigned)nb) pre[k][threadIdx.x] = ex;
+        if (threadIdx.x == 0) pre[k][nb] = tot;
+    }
+    __syncthreads();
+}
+
+__device__ RoundIn round_view(const Dev &d, int r, int32_t (*pre)[kMaxRoundBlocks + 1]) {
+    RoundIn in;
+    int32_t tot[kNumClasses];
+    if (r == 1) {
+        for (int k = 0; k < kNumClasses; ++k) tot[k] = d.ct->class_n[k];
+    } else {
+        for (int k = 0; k < kNumClasses; ++k) tot[k] = pre[k][gridDim.x];
+    }
+    in.total = tot[0] + tot[1] + tot[2];
+    for (int k = 0; k < kNumClasses; ++k) in.wl[k] = tot[k];
+    in.topo = (int64_t)in.total > d.threshold;
+    const int src = r & 1;  // round r reads list (r & 1) written by round r-1
+    for (int k = 0; k < kNumClasses; ++k) {
+        if (r == 1 || in.topo) {
+            in.cv[k].base = d.static_list + d.ct->static_off[k];
+            in.cv[k].pre = nullptr;
+            in.cv[k].cap = 0;
+            in.cv[k].total = d.ct->class_n[k];
+        } else {
+            in.cv[k].base = d.seg_list[src] + d.ct->seg_off[k];
+            in.cv[k].pre = pre[k];
+            in.cv[k].cap = d.ct->seg_cap[k];
+            in.cv[k].total = tot[k];
+        }
+    }
+    return in;
+}
+
+struct Units {
+    int64_t u[kNumUnits];
+    __device__ Units() {
+        for (int i = 0; i < kNumUnits; ++i) u[i] = 0;
+    }
+    // per-workgroup totals into d.units[i][block]
+    __device__ void flush(const Dev &d) {
+        __shared__ unsigned long long s_u[kNumUnits];
+        if (threadIdx.x < kNumUnits) s_u[threadIdx.x] = 0;
+        __syncthreads();
+        for (int i = 0; i < kNumUnits; ++i) {
+            const int64_t s = wave_sum(u[i]);
+            if (lane_id() == 0 && s) atomicAdd(&s_u[i], (unsigned long long)s);
+        }
+        __syncthreads();
+        if (threadIdx.x < kNumUnits) d.units[threadIdx.x * gridDim.x + blockIdx.x] += (int64_t)s_u[threadIdx.x];
+        __syncthreads();
+    }
+};
+
+// Appends of one workgroup's losers into its own segments of the out list.
+struct OutSegs {
+    int32_t *list;     // out list
+    int32_t *cnt;      // its segment counts
+    int64_t *deg;
+    int cls_off[kNumClasses];
+    int cap[kNumClasses];
+};
+
+// ============================================================== step 1: tentative first-fit colors
+//
+// Every uncolored node takes the smallest color >= 1 that no committed
+// neighbour holds (Section II-C with its footnote on mex; 0 marks uncolored).
+
+__device__ void assign_step(const Dev &d, const RoundIn &in, Units &un) {
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gw = gt / kWave, nw = nt / kWave;
+    const int lane = lane_id();
+    // class L: a thread per node, colors read from the row
+    for (int64_t i = gt; i < in.cv[kL].total; i += nt) {
+        const int32_t v = in.cv[kL].at((int32_t)i);
+        if (in.topo && d.c[v] > 0) continue;
+        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1];
+        uint64_t used = 0;
+        for (int32_t k = b; k < e; ++k) {
+            const int32_t cu = d.c[d.colidx[k]];
+            if (cu > 0 && cu <= 64) used |= 1ull << (cu - 1);
+        }
+        d.c[v] = -(__ffsll((unsigned long long)~used));  // degree <= 32 leaves a zero bit
+        un.u[kUAssignNodes] += 1;
+        un.u[kUPullEntries] += e - b;
+    }
+    // classes W and M: a wavefront per node, first free byte of the byte map
+    const int32_t nW = in.cv[kW].total, nWM = nW + in.cv[kM].total;
+    for (int64_t i = gw; i < nWM; i += nw) {
+        const int32_t v = i < nW ? in.cv[kW].at((int32_t)i) : in.cv[kM].at((int32_t)(i - nW));
+        const int32_t cv = d.c[v];
+        if (in.topo && cv > 0) continue;
+        const uint2 fm = d.fmeta[v];
+        uint32_t s = cv < 0 ? (uint32_t)(-cv) - 1u : 0u;  // the previous tentative color, 0-based
+        int32_t t = (int32_t)fm.y;  // d + 1 is free if nothing smaller is
+        for (; s < fm.y; s += kWave) {
+            const uint32_t idx = s + lane;
+            const uint8_t used = idx < fm.y ? d.F[(uint64_t)fm.x + idx] : 0;
+            const uint64_t fz = __ballot(used == 0);
+            un.u[kUMapBytes] += lane == 0 ? kWave : 0;
+            if (fz) {
+                t = (int32_t)(s + __ffsll((unsigned long long)fz));
+                break;
+            }
+        }
+        if (lane == 0) {
+            d.c[v] = -t;
+            un.u[kUAssignNodes] += 1;
+        }
+    }
+}
+
+// ============================================================== step 2: conflicts, commit, push
+//
+// v loses iff a smaller neighbour u holds the same tentative color (the lower
+// id keeps its color).  Winners commit; W and L winners write their color into
+// the byte maps of their neighbours at once, M winners are recorded for the
+// push step; losers go to the workgroup's segment of the out list.
+
+__device__ __forceinline__ void push_color(const Dev &d, int32_t w, int32_t t) {
+    const uint2 fm = d.fmeta[w];
+    if ((uint32_t)t <= fm.y) d.F[(uint64_t)fm.x + t - 1] = 1;
+}
+
+// Ring scan of W/M node v by one wavefront: looks for a smaller neighbour with
+// tentative color t, drops committed neighbours, keeps the others (moved to the
+// ring's end) and advances the ring start past every entry it read.  Reads at
+// least one chunk; stops after the chunk in which a conflict shows up.
+__device__ bool ring_scan_wave(const Dev &d, int32_t v, int32_t t, Units &un) {
+    const int lane = lane_id();
+    const int32_t base = d.rowptr[v], cap = d.rowptr[v + 1] - base;
+    int32_t start = d.lstart[v], len = d.llen[v];
+    int32_t read = 0, kept = 0;
+    bool lose = false;
+    while (read < len && !lose) {
+        const int32_t k = read + lane;
+        int32_t u = -1, cu = 0;
+        if (k < len) {
+            int32_t p = start + k;
+            if (p >= cap) p -= cap;
+            u = d.lower[base + p];
+            cu = d.c[u];
+        }
+        const bool hit = u >= 0 && iabs(cu) == t;
+        const bool keep = u >= 0 && cu < 0;
+        lose = __ballot(hit) != 0;
+        const uint64_t km = __ballot(keep);
+        if (keep) {
+            int32_t p = start + len + kept + __popcll(km & lanes_below());
+            while (p >= cap) p -= cap;
+            d.lower[base + p] = u;
+        }
+        kept += __popcll(km);
+        read += min(kWave, len - read);
+    }
+    un.u[kUConflictEntries] += lane == 0 ? read : 0;
+    un.u[kUListWrites] += lane == 0 ? kept : 0;
+    if (lane == 0 && len > 0) {
+        int32_t s2 = start + read;
+        if (s2 >= cap) s2 -= cap;
+        d.lstart[v] = s2;
+        d.llen[v] = len - read + kept;
+    }
+    return lose;
+}
+
+__device__ void conflict_step(const Dev &d, const RoundIn &in, const OutSegs &os, Units &un) {
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gw = gt / kWave, nw = nt / kWave;
+    const int lane = lane_id();
+    __shared__ int s_cnt[kNumClasses];
+    __shared__ unsigned long long s_deg[kNumClasses];
+    if (threadIdx.x < kNumClasses) {
+        s_cnt[threadIdx.x] = 0;
+        s_deg[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    const int32_t seg_base[kNumClasses] = {os.cls_off[kL] + (int32_t)blockIdx.x * os.cap[kL],
+                                           os.cls_off[kW] + (int32_t)blockIdx.x * os.cap[kW],
+                                           os.cls_off[kM] + (int32_t)blockIdx.x * os.cap[kM]};
+
+    // classes W and M: a wavefront per node.  W winners write their color into
+    // their neighbours' byte maps at once; M winners are recorded for the push step.
+    const int32_t nW = in.cv[kW].total, nWM = nW + in.cv[kM].total;
+    for (int64_t i = gw; i < nWM; i += nw) {
+        const bool hub = i >= nW;
+        const int32_t v = hub ? in.cv[kM].at((int32_t)(i - nW)) : in.cv[kW].at((int32_t)i);
+        const int32_t cv = d.c[v];
+        if (in.topo && cv > 0) continue;
+        const int32_t t = -cv;
+        const bool lose = ring_scan_wave(d, v, t, un);
+        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1];
+        const int q = hub ? kM : kW;
+        if (lane == 0) un.u[kUConflictNodes] += 1;
+        if (lose) {
+            if (lane == 0) {
+                const int p = atomicAdd(&s_cnt[q], 1);
+                atomicAdd(&s_deg[q], (unsigned long long)(e - b));
+                os.list[seg_base[q] + p] = v;
+            }
+        } else {
+            if (lane == 0) {
+                d.c[v] = t;
+                un.u[kUCommits] += 1;
+            }
+            if (hub) {
+                if (lane == 0) d.hub_won[atomicAdd(&d.ct->hub_winners, 1)] = v;
+            } else {
+                for (int32_t k = b + lane; k < e; k += kWave) push_color(d, d.colidx[k], t);
+                un.u[kUPushEntries] += lane == 0 ? e - b : 0;
+            }
+        }
+    }
+    // class L: a thread per node
+    for (int64_t i = gt; i < in.cv[kL].total; i += nt) {
+        const int32_t v = in.cv[kL].at((int32_t)i);
+        const int32_t cv = d.c[v];
+        if (in.topo && cv > 0) continue;
+        const int32_t t = -cv;
+        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1];
+        bool lose = false;
+        int32_t k = b;
+        for (; k < e; ++k) {
+            const int32_t u = d.colidx[k];
+            if (u >= v) {
+                if (d.sorted) break;
+                continue;
+            }
+            if (iabs(d.c[u]) == t) {
+                lose = true;
+                break;
+            }
+        }
+        un.u[kUConflictNodes] += 1;
+        un.u[kUConflictEntries] += k - b + (k < e ? 1 : 0);
+        if (lose) {
+            const int p = atomicAdd(&s_cnt[kL], 1);
+            atomicAdd(&s_deg[kL], (unsigned long long)(e - b));
+            os.list[seg_base[kL] + p] = v;
+        } else {
+            d.c[v] = t;
+            un.u[kUCommits] += 1;
+            for (int32_t j = b; j < e; ++j) push_color(d, d.colidx[j], t);
+            un.u[kUPushEntries] += e - b;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kNumClasses) {
+        os.cnt[threadIdx.x * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
+        os.deg[threadIdx.x * gridDim.x + blockIdx.x] = (int64_t)s_deg[threadIdx.x];
+    }
+}
+
+// Push step: the rows of this round's committed hubs, spread over every
+// wavefront of the grid, 64 entries per wavefront at a time.
+__device__ void hub_push_step(const Dev &d, int32_t nwon, Units &un) {
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int lane = lane_id();
+    for (int32_t h = 0; h < nwon; ++h) {
+        const int32_t v = d.hub_won[h];
+        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1], t = d.c[v];
+        // chunk j (64 entries) of hub h goes to wavefront (j + 7919 h) mod nw, so that the
+        // first chunks of different hubs land on different wavefronts
+        const int64_t j0 = (gw - ((int64_t)h * 7919) % nw + nw) % nw;
+        for (int64_t k0 = (int64_t)b + j0 * kWave; k0 < e; k0 += nw * kWave) {
+            const int64_t k = k0 + lane;
+            if (k < e) push_color(d, d.colidx[k], t);
+        }
+        if (j0 == 0 && lane == 0) un.u[kUPushEntries] += e - b;
+    }
+}
+
+// ============================================================== round kernels
+
+// Round bookkeeping by workgroup 0 (all its threads): trace, work units, and
+// the stop test (a round that starts with an empty worklist is not run).
+__device__ void round_record(const Dev &d, int r, const RoundIn &in, bool reset_hubs) {
+    __shared__ unsigned long long s_deg[kNumClasses];
+    if (in.total == 0) {
+        if (threadIdx.x == 0) {
+            d.ct->finished = 1;
+            d.ct->rounds = r - 1;
+        }
+        return;
+    }
+    if (threadIdx.x < kNumClasses) s_deg[threadIdx.x] = 0;
+    __syncthreads();
+    if (r > 1) {
+        for (int k = 0; k < kNumClasses; ++k) {
+            const int64_t x = threadIdx.x < gridDim.x ? d.seg_deg[r & 1][k * gridDim.x + threadIdx.x] : 0;
+            const int64_t ws = wave_sum(x);
+            if (lane_id() == 0 && ws) atomicAdd(&s_deg[k], (unsigned long long)ws);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t dsum = 0;
+        for (int k = 0; k < kNumClasses; ++k) {
+            const int64_t ds = r == 1 ? d.ct->class_deg[k] : (int64_t)s_deg[k];
+            dsum += ds;
+            d.ct->unit_nodes[k] += in.wl[k];
+            d.ct->unit_edges[k] += ds;
+        }
+        if (r - 1 < d.trace_cap) {
+            d.trace[r - 1] = in.total;
+            d.trace_deg[r - 1] = dsum;
+        }
+        if (reset_hubs) d.ct->hub_winners = 0;
+    }
+}
+
+__device__ OutSegs out_segs(const Dev &d, int r) {
+    OutSegs os;
+    const int dst = (r + 1) & 1;  // round r writes the list round r+1 reads
+    os.list = d.seg_list[dst];
+    os.cnt = d.seg_cnt[dst];
+    os.deg = d.seg_deg[dst];
+    for (int k = 0; k < kNumClasses; ++k) {
+        os.cls_off[k] = d.ct->seg_off[k];
+        os.cap[k] = d.ct->seg_cap[k];
+    }
+    return os;
+}
+
+__device__ __forceinline__ void tick(const Dev &d, int64_t i) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && i < d.tick_cap) d.ticks[i] = wall_clock64();
+}
+
+// Every round in one cooperative launch: assign | barrier | conflict | barrier
+// [| hub push | barrier].  Every workgroup reads the same counts after each
+// barrier, so all take the same branches and leave the loop together.
+__global__ __launch_bounds__(kRoundBlock) void k_rounds(Dev d, int32_t max_rounds) {
+    __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
+    GridBarrier gb;
+    gb.setup(d.bar);
+    Units un;
+    int32_t r = 1;
+    for (; r <= max_rounds; ++r) {
+        if (r > 1) load_segments(d, r & 1, pre);
+        const RoundIn in = round_view(d, r, pre);
+        if (blockIdx.x == 0) round_record(d, r, in, false);
+        if (in.total == 0) break;
+        tick(d, 3 * (int64_t)(r - 1));
+        assign_step(d, in, un);
+        gb.sync();
+        tick(d, 3 * (int64_t)(r - 1) + 1);
+        conflict_step(d, in, out_segs(d, r), un);
+        gb.sync();
+        tick(d, 3 * (int64_t)(r - 1) + 2);
+        // every workgroup reads the count here; it is cleared only after the next barrier
+        const int32_t nwon = (int32_t)ld_agent((unsigned *)&d.ct->hub_winners);
+        if (nwon > 0) {
+            hub_push_step(d, nwon, un);
+            gb.sync();
+            if (blockIdx.x == 0 && threadIdx.x == 0) d.ct->hub_winners = 0;
+        }
+    }
+    tick(d, 3 * (int64_t)(r - 1));
+    un.flush(d);
+}
+
+// The same steps as separate launches (the launch boundary is the barrier),
+// for hosts that cannot launch cooperatively and for per-step timing.
+__global__ __launch_bounds__(kRoundBlock) void k_assign_round(Dev d, int32_t r) {
+    if (d.ct->finished) return;
+    __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
+    if (r > 1) load_segments(d, r & 1, pre);
+    const RoundIn in = round_view(d, r, pre);
+    if (blockIdx.x == 0) round_record(d, r, in, true);
+    if (in.total == 0) return;
+    Units un;
+    assign_step(d, in, un);
+    un.flush(d);
+}
+
+__global__ __launch_bounds__(kRoundBlock) void k_conflict_round(Dev d, int32_t r) {
+    if (d.ct->finished) return;
+    __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
+    if (r > 1) load_segments(d, r & 1, pre);
+    const RoundIn in = round_view(d, r, pre);
+    if (in.total == 0) return;
+    Units un;
+    conflict_step(d, in, out_segs(d, r), un);
+    un.flush(d);
+}
+
+__global__ __launch_bounds__(kRoundBlock) void k_push_round(Dev d) {
+    if (d.ct->finished) return;
+    const int32_t nwon = d.ct->hub_winners;
+    if (nwon == 0) return;
+    Units un;
+    hub_push_step(d, nwon, un);
+    un.flush(d);
+}
+
+}  // namespace ipgc

@@ -47,7 +47,7 @@ def test_struct_layouts():
     import paper_1912_01478_amd as pkg
     assert ctypes.sizeof(pkg.Options) == 32
     assert ctypes.sizeof(pkg.Trace) == 40
-    assert ctypes.sizeof(pkg.Profile) == 8 + 8 * 16 * 4
+    assert ctypes.sizeof(pkg.Profile) == 8 + 8 * 16 * 2 + 8 + 8 * 16 + 32
 
 
 def test_kernel_names(lib):
@@ -58,6 +58,12 @@ def test_kernel_names(lib):
         k += 1
     assert len(names) >= 4 and len(set(names)) == len(names)
     assert lib.ipgc_kernel_name(-1) == b"" and lib.ipgc_kernel_name(99) == b""
+    units = []
+    k = 0
+    while lib.ipgc_unit_name(k):
+        units.append(lib.ipgc_unit_name(k).decode())
+        k += 1
+    assert len(units) >= 4 and len(set(units)) == len(units)
 
 
 def test_product_package_does_not_import_oracle():

@@ -111,10 +111,17 @@ def test_random_parity(g, mode):
 
 
 @pytest.mark.parametrize("H", [1, 100, 5000, 10**9])
-@pytest.mark.parametrize("light,wave", [(1, 2), (8, 64), (32, 1024), (63, 2047)])
-def test_options_never_change_the_result(H, light, wave):
+@pytest.mark.parametrize("light,hub", [(1, 2), (8, 64), (32, 4096), (16, 100000)])
+def test_options_never_change_the_result(H, light, hub):
     g = SMALL[3]
-    assert_parity(g, "hybrid", threshold=H, light_max_degree=light, wave_max_degree=wave)
+    assert_parity(g, "hybrid", threshold=H, light_max_degree=light, hub_min_degree=hub)
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("g", SMALL, ids=lambda g: g.name)
+def test_stepped_launches_same_result(g, mode):
+    """One launch per round step (no grid barriers) gives the same result as the cooperative loop."""
+    assert_parity(g, mode, stepped=True, light_max_degree=4, hub_min_degree=300)
 
 
 @pytest.mark.parametrize("g", SMALL[:4], ids=lambda g: g.name)
@@ -181,7 +188,10 @@ def test_errors():
         ip.color_graph(rp3, ci, "hybrid")
     assert e.value.code == -3
     with pytest.raises(ip.IpgcError) as e:
-        ip.color_graph(rp, ci, "hybrid", light_max_degree=64)
+        ip.color_graph(rp, ci, "hybrid", light_max_degree=33)
+    assert e.value.code == -1
+    with pytest.raises(ip.IpgcError) as e:
+        ip.color_graph(rp, ci, "hybrid", light_max_degree=8, hub_min_degree=8)
     assert e.value.code == -1
     # the library still works after errors
     assert_parity(g, "hybrid")
