@@ -26,16 +26,58 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
-# Algorithmic bytes per work unit counted on the device ("Measurement").
-#   assign_nodes      worklist entry (or state read of a sweep) 4 + row bounds 8 + state write 4
-#   pull_entries      column index 4 + neighbour state 4           (thread-per-node assign)
-#   map_bytes         one byte-map byte read                       (first free color of W/M nodes)
+# Algorithmic bytes of the method (SURVEY-style per-unit figures):
+# per round r, 36 bytes per active node and 16 bytes per row entry of an active node:
+#   assign   worklist entry 4 + row bounds 8 + tentative write 4 per node; column index 4 +
+#            neighbour color 4 per entry
+#   conflict worklist entry 4 + row bounds 8 + own tentative 4 + commit or push 4 per node;
+#            column index 4 + neighbour tentative 4 per entry
+MODEL_NODE_BYTES = 36
+MODEL_ENTRY_BYTES = 16
+
+# Bytes per work unit the implementation itself counts on the device (what this design reads
+# and writes without cache effects), reported beside the model.
+#   assign_nodes      worklist entry 4 + row bounds 8 + state write 4
+#   pull_entries      column index 4 + neighbour state 4
+#   map_bytes         one byte-map byte read
 #   conflict_nodes    list entry 4 + bounds 8 + own state 4 + commit or worklist push 4
 #   conflict_entries  list entry 4 + neighbour state 4
 #   list_writes       one kept list entry written back 4
 #   push_entries      column index 4 + neighbour byte-map metadata 8 + byte store 1
 UNIT_BYTES = {"assign_nodes": 16, "pull_entries": 8, "map_bytes": 1, "conflict_nodes": 20,
               "conflict_entries": 8, "list_writes": 4, "push_entries": 13, "commits": 0}
+
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1912_01478_amd", "csrc", f) for f in ("ipgc_device.hpp", "ipgc.hip")]
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(workload: str):
+    """HBM bytes per launch of the round kernel from the committed rocprofv3 counter summary, if
+    it was taken from the current kernel source (else None)."""
+    path = os.path.join(PROFILE_DIR, "k_rounds_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    start = text.find("```json")
+    if start < 0:
+        return None
+    block = text[start + 7:text.find("```", start + 7)]
+    try:
+        data = json.loads(block)
+    except ValueError:
+        return None
+    if data.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return data.get("traffic_bytes_per_launch")
 
 
 def log(*a):
@@ -54,6 +96,8 @@ def parse():
     p.add_argument("--cpu-sample-fraction", type=float, default=0.15,
                    help="fraction of the algorithmic bytes the CPU oracle sample covers")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--copy-mib", type=int, default=0,
+                   help="also run one plain device copy of this many MiB (a reference for HBM byte counters)")
     return p.parse_args()
 
 
@@ -115,22 +159,27 @@ def main():
     # per-kernel profile and trace of one more (untimed) call
     prof = pkg.color_graph(rp, ci, args.mode, out=out, trace=True, profile_mask=0xFFFF)
     units = prof.profile["units"]
-    alg_round_bytes = sum(UNIT_BYTES.get(k, 0) * v for k, v in units.items())
+    work_bytes = sum(UNIT_BYTES.get(k, 0) * v for k, v in units.items())
     kinds = {}
     for name, p in prof.profile["kernels"].items():
         if p["launches"] == 0:
             continue
         kinds[name] = {"ms": round(p["ms"], 4), "launches": p["launches"], "avg_us": round(1000 * p["ms"] / p["launches"], 2)}
-    dom = max(kinds, key=lambda k: kinds[k]["ms"])
-    kd = kinds[dom]
-    alg = alg_round_bytes / kd["launches"] if dom in ("rounds",) else None
-    achieved = round(alg / (kd["avg_us"] * 1e3), 1) if alg else None
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None, "traffic": None,
-                "alg_bytes_per_launch": alg, "avg_launch_us": kd["avg_us"], "launches": kd["launches"]}
     wl = np.asarray(prof.wl_sizes, dtype=np.int64)
     wd = np.asarray(prof.wl_degrees, dtype=np.int64)
-    pull_model_bytes = int(36 * wl.sum() + 16 * wd.sum())
+    model_bytes = int(MODEL_NODE_BYTES * wl.sum() + MODEL_ENTRY_BYTES * wd.sum())
+    dom = max(kinds, key=lambda k: kinds[k]["ms"])
+    kd = kinds[dom]
+    # the round kernel runs every round in one launch, so its per-launch units are the whole run's
+    alg = model_bytes / kd["launches"] if dom == "rounds" else None
+    achieved = round(alg / (kd["avg_us"] * 1e3), 1) if alg else None
+    traffic = committed_traffic(g.name) if dom == "rounds" else None
+    roofline = {"bound": "hbm", "kernel": "k_rounds" if dom == "rounds" else dom, "achieved": achieved,
+                "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None, "traffic": traffic,
+                "alg_bytes_per_launch": alg, "avg_launch_us": kd["avg_us"], "launches": kd["launches"],
+                "work_bytes_per_launch": work_bytes / kd["launches"] if dom == "rounds" else None,
+                "work_GBps": round(work_bytes / kd["launches"] / (kd["avg_us"] * 1e3), 1) if dom == "rounds" else None}
 
     modes = {args.mode: {"ms_per_step": round(ms, 3), "edges_per_s": g.m / (ms / 1000.0)}}
     if args.compare_steps > 0:
@@ -142,10 +191,21 @@ def main():
             modes[other] = {"ms_per_step": round(oms, 3), "edges_per_s": g.m / (oms / 1000.0)}
             log("%s: %.3f ms/step" % (other, oms))
 
+    if args.copy_mib > 0:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counter readings calibrate the
+        # counters of the coloring kernels (read args.copy_mib MiB, write args.copy_mib MiB)
+        src_t = torch.ones(args.copy_mib << 18, dtype=torch.int32, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        torch.cuda.synchronize()
+        dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        log("copy of %d MiB done" % args.copy_mib)
+        del src_t, dst_t
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        cum = np.cumsum(36 * wl + 16 * wd)
+        cum = np.cumsum(MODEL_NODE_BYTES * wl + MODEL_ENTRY_BYTES * wd)
         k = int(np.searchsorted(cum, args.cpu_sample_fraction * cum[-1]) + 1)
         k = max(1, min(k, len(wl)))
         frac = float(cum[k - 1] / cum[-1])
@@ -170,7 +230,6 @@ def main():
         if "data" in modes and "hybrid" in modes else None,
         "roofline": roofline,
         "work_units": units,
-        "pull_model_bytes": pull_model_bytes,
         "kernels": kinds,
         "cpu_baseline": cpu,
     }

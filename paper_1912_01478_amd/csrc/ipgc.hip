@@ -9,13 +9,16 @@
 //   k_init        initial state, node classes, row-pointer checks, class counts
 //   k_offsets     prefix sums of the class counts, list layouts
 //   k_fill_static every node grouped by class, ascending ids
-//   k_check       column ids in range, sorted rows (unless validation is off)
-//   k_prep_wide   byte maps and smaller-neighbour rings of W/M nodes
+//   k_check_light column ids in range and sorted rows, light rows (unless
+//                 validation is off)
+//   k_prep_wide   smaller-neighbour rings of W/M nodes, with the same checks
+//                 of their rows
 //   k_rounds      every round, one cooperative launch with grid barriers
 //                 (or k_assign_round + k_conflict_round + k_push_round per
 //                 round when stepped)
-// and read back the round count.  The host synchronizes twice: after the
-// checks (their verdict decides whether to go on) and after the rounds.
+// and read back the round count.  The host synchronizes after the row-pointer
+// checks (rows are only read through valid pointers), after the column checks
+// (their verdict decides whether to go on) and after the rounds.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -93,7 +96,8 @@ struct DBuf {
 };
 
 struct Workspace {
-    DBuf<int32_t> static_list, seg_list0, seg_list1, seg_cnt, hub_won, block_cnt, trace, lstart, llen, lower;
+    DBuf<int32_t> static_list, seg_list0, seg_list1, seg_cnt, block_cnt, trace, lstart, llen, lower;
+    DBuf<int4> hub_won;
     DBuf<int64_t> seg_deg, block_deg, units, trace_deg;
     DBuf<int8_t> cls;
     DBuf<uint2> fmeta;
@@ -124,7 +128,7 @@ struct Workspace {
         TRY(trace_deg.reserve(n));
         TRY(cls.reserve(n));
         TRY(fmeta.reserve(n));
-        TRY(F.reserve(m + n));
+        TRY(F.reserve(m + n + 64));  // word reads may run 3 bytes past the last map
         TRY(lower.reserve(m));
         TRY(lstart.reserve(n));
         TRY(llen.reserve(n));
@@ -321,6 +325,7 @@ int color_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t 
     HIP_TRY(hipMemsetAsync(ws.ct, 0, sizeof(Counters), s));
     HIP_TRY(hipMemsetAsync(ws.bar.p, 0, sizeof(Barrier), s));
     HIP_TRY(hipMemsetAsync(ws.units.p, 0, sizeof(int64_t) * kNumUnits * grid, s));
+    HIP_TRY(hipMemsetAsync(ws.F.p, 0, (size_t)(m + n + 64), s));  // every byte map starts empty
     TRY(pf.begin(kKindInit));
     k_init<<<prep_grid, kPrepBlock, 0, s>>>(d, ws.cls.p, ws.fmeta.p, (int32_t)span);
     k_offsets<<<1, 1024, 0, s>>>(d, prep_grid);
@@ -330,23 +335,25 @@ int color_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t 
     // k_check reads rows through rowptr, so it only runs on row pointers that passed k_init
     TRY(read_counters(ws, s));
     if (ws.host_ct->bad_rows) return fail(IPGC_EBADCSR, "rowptr is decreasing or outside [0, m]");
-    const int check_grid = (int)std::min<int64_t>(8192, (n + kPrepBlock - 1) / kPrepBlock);
-    if (check_ids) {
+    const int64_t n_light = ws.host_ct->class_n[kL];
+    const int64_t n_wide = (int64_t)ws.host_ct->class_n[kW] + ws.host_ct->class_n[kM];
+    if (check_ids && n_light > 0) {
         TRY(pf.begin(kKindCheck));
-        k_check<<<check_grid, kPrepBlock, 0, s>>>(d);
+        k_check_light<<<(int)std::min<int64_t>(8192, (n_light + kPrepBlock - 1) / kPrepBlock), kPrepBlock, 0, s>>>(d);
         TRY(pf.end(kKindCheck));
         HIP_TRY(hipGetLastError());
-        TRY(read_counters(ws, s));
-        if (ws.host_ct->bad_ids) return fail(IPGC_EBADCSR, "a column id is outside [0, n)");
     }
-    d.sorted = check_ids && !ws.host_ct->unsorted;
-    const int64_t n_wide = (int64_t)ws.host_ct->class_n[kW] + ws.host_ct->class_n[kM];
-    if (n_wide > 0) {
+    if (n_wide > 0) {  // also checks the ids of the wide rows
         TRY(pf.begin(kKindPrep));
         k_prep_wide<<<(int)std::min<int64_t>(8192, (n_wide + 3) / 4), kPrepBlock, 0, s>>>(d);
         TRY(pf.end(kKindPrep));
         HIP_TRY(hipGetLastError());
     }
+    if (check_ids) {
+        TRY(read_counters(ws, s));
+        if (ws.host_ct->bad_ids) return fail(IPGC_EBADCSR, "a column id is outside [0, n)");
+    }
+    d.sorted = check_ids && !ws.host_ct->unsorted;
 
     // Rounds: at most n (the worklist shrinks every round), plus the start of the one that finds it empty.
     if (coop > 0) {

@@ -115,7 +115,7 @@ struct Dev {
     const int32_t *colidx;
     int32_t *c;              // color state (caller's output)
     const int8_t *cls;       // class per node
-    const uint2 *fmeta;      // {byte-map base, byte-map size = d+1} per node; size 0 for class L
+    const uint2 *fmeta;      // {byte-map base, byte-map size = d+1} per node
     uint8_t *F;              // byte maps
     int32_t *lower;          // ring of smaller neighbours per W/M node (region rowptr[v] .. + d)
     int32_t *lstart;         // ring start per node
@@ -124,7 +124,7 @@ struct Dev {
     int32_t *seg_list[2];    // the two alternating segmented worklists
     int32_t *seg_cnt[2];     // [kNumClasses][grid] entries per segment
     int64_t *seg_deg[2];     // [kNumClasses][grid] degree sum per segment
-    int32_t *hub_won;        // hubs committed in the current round
+    int4 *hub_won;           // hubs committed in the current round: {node, row begin, row end, color}
     int32_t *block_cnt;      // [kNumClasses][prep grid] class counts per preparation workgroup
     int64_t *block_deg;      // [kNumClasses][prep grid]
     int64_t *units;          // [kNumUnits][grid] work counters per round workgroup
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_init(Dev d, int8_t *cls, uint2 *
         const int64_t dv = b ? 0 : e - a;
         const int k = node_class(dv, d.light_max, d.hub_min);
         cls[v] = (int8_t)k;
-        fmeta[v] = k == kL ? make_uint2(0u, 0u) : make_uint2((uint32_t)a + (uint32_t)v, (uint32_t)dv + 1u);
+        fmeta[v] = make_uint2((uint32_t)a + (uint32_t)v, (uint32_t)dv + 1u);
         cnt[k] += 1;
         deg[k] += dv;
     }
@@ -362,79 +362,86 @@ __global__ __launch_bounds__(kPrepBlock) void k_fill_static(Dev d, int32_t span)
     }
 }
 
-// Column checks: ids inside [0, n) and strictly ascending rows.  Light rows a
-// thread each, wider rows a wavefront each.
-__global__ __launch_bounds__(kPrepBlock) void k_check(Dev d) {
+// Column checks of light rows (a thread each, four independent loads in
+// flight): ids inside [0, n) and strictly ascending rows.  Wider rows are
+// checked by k_prep_wide while it reads them.
+__global__ __launch_bounds__(kPrepBlock) void k_check_light(Dev d) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
-    const int64_t gw = gt / kWave, nw = nt / kWave;
-    const int lane = lane_id();
     int bad = 0, unsorted = 0;
     const int32_t nL = d.ct->class_n[kL];
     const int32_t *listL = d.static_list + d.ct->static_off[kL];
     for (int64_t i = gt; i < nL; i += nt) {
         const int32_t v = listL[i];
-        int32_t prev = -1;
-        for (int32_t k = d.rowptr[v]; k < d.rowptr[v + 1]; ++k) {
-            const int32_t u = d.colidx[k];
-            bad |= (u < 0 || u >= d.n);
-            unsorted |= (u <= prev);
-            prev = u;
-        }
-    }
-    const int32_t nWide = d.ct->class_n[kW] + d.ct->class_n[kM];
-    const int32_t *listWide = d.static_list + d.ct->static_off[kW];
-    for (int64_t i = gw; i < nWide; i += nw) {
-        const int32_t v = listWide[i];
         const int32_t b = d.rowptr[v], e = d.rowptr[v + 1];
-        for (int32_t k = b + lane; k < e; k += kWave) {
-            const int32_t u = d.colidx[k];
-            bad |= (u < 0 || u >= d.n);
-            if (k + 1 < e) unsorted |= (d.colidx[k + 1] <= u);
+        int32_t prev = -1;
+        for (int32_t k0 = b; k0 < e; k0 += 4) {
+            int32_t u[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) u[j] = k0 + j < e ? d.colidx[k0 + j] : INT32_MAX;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (u[j] == INT32_MAX && k0 + j >= e) continue;
+                bad |= (u[j] < 0 || u[j] >= d.n);
+                unsorted |= (u[j] <= prev);
+                prev = u[j];
+            }
         }
     }
-    if (__ballot(bad) && lane == 0) d.ct->bad_ids = 1;
-    if (__ballot(unsorted) && lane == 0) d.ct->unsorted = 1;
+    if (__ballot(bad) && lane_id() == 0) d.ct->bad_ids = 1;
+    if (__ballot(unsorted) && lane_id() == 0) d.ct->unsorted = 1;
 }
 
-// Per W/M node (a wavefront each): clear its byte map and copy its smaller
-// neighbours into its ring, neighbours of class W or M first.
+// Per W/M node (a wavefront each), in one pass over its row: check the ids
+// (inside [0, n), strictly ascending) and fill its ring of smaller neighbours.
+// Within the node's region [0, d), smaller neighbours of class L are written
+// upward from position 0 and those of class W or M downward from position
+// d - 1 and then reversed, so the ring starts at the W/M part and wraps around
+// into the L part, both in ascending id order: neighbours of high degree come
+// first in every scan.
 __global__ __launch_bounds__(kPrepBlock) void k_prep_wide(Dev d) {
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
     const int lane = lane_id();
     const int32_t nWide = d.ct->class_n[kW] + d.ct->class_n[kM];
     const int32_t *listWide = d.static_list + d.ct->static_off[kW];
+    int bad = 0, unsorted = 0;
     for (int64_t i = gw; i < nWide; i += nw) {
         const int32_t v = listWide[i];
-        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1];
-        const uint2 fm = d.fmeta[v];
-        for (uint32_t k = lane; k < fm.y; k += kWave) d.F[(uint64_t)fm.x + k] = 0;
-        int32_t nwide = 0;
+        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1], cap = e - b;
+        int32_t nl = 0, nh = 0;  // smaller neighbours of class L / of class W or M written so far
         for (int32_t k0 = b; k0 < e; k0 += kWave) {
             const int32_t k = k0 + lane;
-            const bool first = k < e && d.colidx[k] < v && d.cls[d.colidx[k]] != kL;
-            nwide += __popcll(__ballot(first));
-        }
-        int32_t pos_wide = 0, pos_light = nwide;
-        for (int32_t k0 = b; k0 < e; k0 += kWave) {
-            const int32_t k = k0 + lane;
-            int32_t u = -1;
             int q = -1;
+            int32_t u = -1;
             if (k < e) {
                 u = d.colidx[k];
-                if (u < v) q = d.cls[u] != kL ? 0 : 1;
+                const bool ok = u >= 0 && u < d.n;
+                bad |= !ok;
+                if (k + 1 < e) unsorted |= (d.colidx[k + 1] <= u);
+                if (ok && u < v) q = d.cls[u] == kL ? 0 : 1;
             }
             const uint64_t m0 = __ballot(q == 0), m1 = __ballot(q == 1);
-            if (q == 0) d.lower[b + pos_wide + __popcll(m0 & lanes_below())] = u;
-            if (q == 1) d.lower[b + pos_light + __popcll(m1 & lanes_below())] = u;
-            pos_wide += __popcll(m0);
-            pos_light += __popcll(m1);
+            if (q == 0) d.lower[b + nl + __popcll(m0 & lanes_below())] = u;
+            if (q == 1) d.lower[b + cap - 1 - (nh + __popcll(m1 & lanes_below()))] = u;
+            nl += __popcll(m0);
+            nh += __popcll(m1);
+        }
+        // the W/M part was written downward; reverse it so both parts run in ascending id order
+        {
+            int32_t *wm = d.lower + b + cap - nh;
+            for (int32_t j = lane; j < nh / 2; j += kWave) {
+                const int32_t x = wm[j], y = wm[nh - 1 - j];
+                wm[j] = y;
+                wm[nh - 1 - j] = x;
+            }
         }
         if (lane == 0) {
-            d.lstart[v] = 0;
-            d.llen[v] = pos_light;
+            d.lstart[v] = nh > 0 ? cap - nh : 0;
+            d.llen[v] = nl + nh;
         }
     }
+    if (__ballot(bad) && lane == 0) d.ct->bad_ids = 1;
+    if (__ballot(unsorted) && lane == 0) d.ct->unsorted = 1;
 }
 
 // ============================================================== worklist views
@@ -544,23 +551,40 @@ struct OutSegs {
 // Every uncolored node takes the smallest color >= 1 that no committed
 // neighbour holds (Section II-C with its footnote on mex; 0 marks uncolored).
 
+// First zero byte of a node's byte map at or after index s (colors are the
+// index + 1).  Reads aligned 4-byte words; bytes before s and past the map end
+// count as taken.  A free byte exists: a node of degree d sees at most d colors.
+__device__ __forceinline__ int32_t first_free_word(const uint8_t *F, uint2 fm, uint32_t s, Units &un) {
+    const uint64_t end = (uint64_t)fm.x + fm.y;
+    uint64_t a = (uint64_t)fm.x + s;
+    for (;;) {
+        const uint64_t wa = a & ~3ull;
+        uint32_t w = *reinterpret_cast<const uint32_t *>(F + wa);
+        un.u[kUMapBytes] += 4;
+        const uint32_t lo = (uint32_t)(a - wa);
+        if (lo) w |= 0xffffffffu >> (32 - 8 * lo);
+        if (end < wa + 4) w |= 0xffffffffu << (8 * (uint32_t)(end - wa));
+        const uint32_t z = (w - 0x01010101u) & ~w & 0x80808080u;
+        // the lowest flagged byte is a zero byte (borrows only flag higher bytes); ffs of its
+        // bit 7 is 8j + 8, so wa + j + 1 - base is the color of byte j
+        if (z) return (int32_t)(wa + (__ffs(z) >> 3) - fm.x);
+        a = wa + 4;
+        if (a >= end) return (int32_t)fm.y;  // unreachable for a consistent map
+    }
+}
+
 __device__ void assign_step(const Dev &d, const RoundIn &in, Units &un) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
     const int64_t gw = gt / kWave, nw = nt / kWave;
     const int lane = lane_id();
-    // class L: a thread per node, colors read from the row
+    // class L: a thread per node, first free byte of the byte map, read a 4-byte word at a time
     for (int64_t i = gt; i < in.cv[kL].total; i += nt) {
         const int32_t v = in.cv[kL].at((int32_t)i);
-        if (in.topo && d.c[v] > 0) continue;
-        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1];
-        uint64_t used = 0;
-        for (int32_t k = b; k < e; ++k) {
-            const int32_t cu = d.c[d.colidx[k]];
-            if (cu > 0 && cu <= 64) used |= 1ull << (cu - 1);
-        }
-        d.c[v] = -(__ffsll((unsigned long long)~used));  // degree <= 32 leaves a zero bit
+        const int32_t cv = d.c[v];
+        if (in.topo && cv > 0) continue;
+        const uint2 fm = d.fmeta[v];
+        d.c[v] = -first_free_word(d.F, fm, cv < 0 ? (uint32_t)(-cv) - 1u : 0u, un);
         un.u[kUAssignNodes] += 1;
-        un.u[kUPullEntries] += e - b;
     }
     // classes W and M: a wavefront per node, first free byte of the byte map
     const int32_t nW = in.cv[kW].total, nWM = nW + in.cv[kM].total;
@@ -598,6 +622,26 @@ __device__ void assign_step(const Dev &d, const RoundIn &in, Units &un) {
 __device__ __forceinline__ void push_color(const Dev &d, int32_t w, int32_t t) {
     const uint2 fm = d.fmeta[w];
     if ((uint32_t)t <= fm.y) d.F[(uint64_t)fm.x + t - 1] = 1;
+}
+
+// Write color t into the byte maps of the neighbours in row entries [b, e),
+// one wavefront, four independent loads in flight per lane.
+__device__ __forceinline__ void push_row_wave(const Dev &d, int64_t b, int64_t e, int32_t t) {
+    const int lane = lane_id();
+    for (int64_t k0 = b; k0 < e; k0 += 4 * kWave) {
+        int32_t w[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t k = k0 + j * kWave + lane;
+            w[j] = k < e ? d.colidx[k] : -1;
+        }
+        uint2 fm[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? d.fmeta[w[j]] : make_uint2(0u, 0u);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if ((uint32_t)t <= fm[j].y) d.F[(uint64_t)fm[j].x + t - 1] = 1;
+    }
 }
 
 // Ring scan of W/M node v by one wavefront: looks for a smaller neighbour with
@@ -682,9 +726,9 @@ __device__ void conflict_step(const Dev &d, const RoundIn &in, const OutSegs &os
                 un.u[kUCommits] += 1;
             }
             if (hub) {
-                if (lane == 0) d.hub_won[atomicAdd(&d.ct->hub_winners, 1)] = v;
+                if (lane == 0) d.hub_won[atomicAdd(&d.ct->hub_winners, 1)] = make_int4(v, b, e, t);
             } else {
-                for (int32_t k = b + lane; k < e; k += kWave) push_color(d, d.colidx[k], t);
+                push_row_wave(d, b, e, t);
                 un.u[kUPushEntries] += lane == 0 ? e - b : 0;
             }
         }
@@ -696,21 +740,28 @@ __device__ void conflict_step(const Dev &d, const RoundIn &in, const OutSegs &os
         if (in.topo && cv > 0) continue;
         const int32_t t = -cv;
         const int32_t b = d.rowptr[v], e = d.rowptr[v + 1];
-        bool lose = false;
-        int32_t k = b;
-        for (; k < e; ++k) {
-            const int32_t u = d.colidx[k];
-            if (u >= v) {
-                if (d.sorted) break;
-                continue;
-            }
-            if (iabs(d.c[u]) == t) {
-                lose = true;
-                break;
+        bool lose = false, done = false;
+        int32_t read = 0;
+        // four neighbours per step: their ids, then their states, then the test in row order
+        for (int32_t k0 = b; k0 < e && !lose && !done; k0 += 4) {
+            int32_t u[4], cu[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) u[j] = k0 + j < e ? d.colidx[k0 + j] : INT32_MAX;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cu[j] = u[j] < v ? d.c[u[j]] : 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (lose || done) continue;
+                if (u[j] >= v) {
+                    if (d.sorted || u[j] == INT32_MAX) done = true;
+                    continue;
+                }
+                ++read;
+                lose = iabs(cu[j]) == t;
             }
         }
         un.u[kUConflictNodes] += 1;
-        un.u[kUConflictEntries] += k - b + (k < e ? 1 : 0);
+        un.u[kUConflictEntries] += read;
         if (lose) {
             const int p = atomicAdd(&s_cnt[kL], 1);
             atomicAdd(&s_deg[kL], (unsigned long long)(e - b));
@@ -718,7 +769,17 @@ __device__ void conflict_step(const Dev &d, const RoundIn &in, const OutSegs &os
         } else {
             d.c[v] = t;
             un.u[kUCommits] += 1;
-            for (int32_t j = b; j < e; ++j) push_color(d, d.colidx[j], t);
+            for (int32_t k0 = b; k0 < e; k0 += 4) {
+                int32_t w[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) w[j] = k0 + j < e ? d.colidx[k0 + j] : -1;
+                uint2 fm[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? d.fmeta[w[j]] : make_uint2(0u, 0u);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if ((uint32_t)t <= fm[j].y) d.F[(uint64_t)fm[j].x + t - 1] = 1;
+            }
             un.u[kUPushEntries] += e - b;
         }
     }
@@ -730,22 +791,42 @@ __device__ void conflict_step(const Dev &d, const RoundIn &in, const OutSegs &os
 }
 
 // Push step: the rows of this round's committed hubs, spread over every
-// wavefront of the grid, 64 entries per wavefront at a time.
+// wavefront of the grid in chunks of 256 entries.  Each workgroup stages up to
+// kRoundBlock hubs at a time (row bounds, color, chunk prefix sums) in shared
+// memory; wavefront w then takes chunks w, w + nw, ... of the staged batch.
 __device__ void hub_push_step(const Dev &d, int32_t nwon, Units &un) {
+    constexpr int kChunk = 4 * kWave;
+    __shared__ int32_t s_b[kRoundBlock], s_e[kRoundBlock], s_t[kRoundBlock], s_pre[kRoundBlock + 1];
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
-    const int lane = lane_id();
-    for (int32_t h = 0; h < nwon; ++h) {
-        const int32_t v = d.hub_won[h];
-        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1], t = d.c[v];
-        // chunk j (64 entries) of hub h goes to wavefront (j + 7919 h) mod nw, so that the
-        // first chunks of different hubs land on different wavefronts
-        const int64_t j0 = (gw - ((int64_t)h * 7919) % nw + nw) % nw;
-        for (int64_t k0 = (int64_t)b + j0 * kWave; k0 < e; k0 += nw * kWave) {
-            const int64_t k = k0 + lane;
-            if (k < e) push_color(d, d.colidx[k], t);
+    for (int32_t h0 = 0; h0 < nwon; h0 += blockDim.x) {
+        const int32_t h = h0 + threadIdx.x;
+        int32_t chunks = 0;
+        if (h < nwon) {
+            const int4 rec = d.hub_won[h];
+            s_b[threadIdx.x] = rec.y;
+            s_e[threadIdx.x] = rec.z;
+            s_t[threadIdx.x] = rec.w;
+            chunks = (rec.z - rec.y + kChunk - 1) / kChunk;
         }
-        if (j0 == 0 && lane == 0) un.u[kUPushEntries] += e - b;
+        int total;
+        const int ex = block_scan(chunks, &total);
+        s_pre[threadIdx.x] = ex;
+        if (threadIdx.x == 0) s_pre[blockDim.x] = total;
+        __syncthreads();
+        const int nh = min((int32_t)blockDim.x, nwon - h0);
+        for (int64_t g = gw; g < total; g += nw) {
+            int lo = 0, hi = nh;  // hub lo with s_pre[lo] <= g < s_pre[lo + 1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (s_pre[mid] <= g) lo = mid;
+                else hi = mid;
+            }
+            const int64_t k0 = (int64_t)s_b[lo] + (g - s_pre[lo]) * kChunk;
+            push_row_wave(d, k0, min<int64_t>(k0 + kChunk, s_e[lo]), s_t[lo]);
+            if (lane_id() == 0) un.u[kUPushEntries] += min<int64_t>(k0 + kChunk, s_e[lo]) - k0;
+        }
+        __syncthreads();
     }
 }
 
