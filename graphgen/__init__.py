@@ -311,3 +311,36 @@ def config_graph(cfg: int, scale_down: int = 0) -> Graph:
         n = 24_000_000 // (4 ** scale_down)
         return road_knn(n, key(3, 0), name="road_knn_n%d" % n)
     raise ValueError("config %r is not a single-graph workload" % cfg)
+
+
+# ---------------------------------------------------------------- batches (config 4)
+
+def _unit(seed_key: int, ctr: int) -> float:
+    return (int(_load().gg_draw(seed_key, ctr)) >> 11) * (1.0 / 9007199254740992.0)
+
+
+def batch_graph_params(cfg: int, i: int, n_min: float = 1e3, n_max: float = 1e6) -> dict:
+    """Parameters of graph i of a batch: n log-uniform in [n_min, n_max]; even i: Erdos-Renyi with
+    average degree uniform in {4..32}; odd i: R-MAT with edge factor uniform in {8..16}."""
+    import math
+    k = key(cfg, i)
+    pk = int(_load().gg_draw(k, 0xBA7C4))  # parameter stream, disjoint from the graph's own draws
+    n = int(round(math.exp(math.log(n_min) + _unit(pk, 0) * (math.log(n_max) - math.log(n_min)))))
+    if i % 2 == 0:
+        return {"kind": "er", "n": n, "avg_degree": 4 + int(_unit(pk, 1) * 29), "key": k}
+    return {"kind": "rmat", "n": n, "edge_factor": 8 + int(_unit(pk, 1) * 9), "key": k}
+
+
+def batch_graph(cfg: int, i: int, n_min: float = 1e3, n_max: float = 1e6) -> Graph:
+    """Graph i of the batch workload (config 4 uses cfg=4, i in [0, 4096))."""
+    import math
+    p = batch_graph_params(cfg, i, n_min, n_max)
+    if p["kind"] == "er":
+        return erdos_renyi(p["n"], float(p["avg_degree"]), p["key"], name="b%d_er_n%d_d%d" % (i, p["n"], p["avg_degree"]))
+    scale = max(1, math.ceil(math.log2(p["n"])))
+    return rmat(scale, p["edge_factor"], p["key"], n=p["n"], name="b%d_rmat_n%d_ef%d" % (i, p["n"], p["edge_factor"]))
+
+
+def batch_graphs(cfg: int = 4, count: int = 4096, n_min: float = 1e3, n_max: float = 1e6, first: int = 0):
+    """Graphs first .. first+count-1 of the batch workload (config 4: 4096 graphs, n in [1e3, 1e6])."""
+    return [batch_graph(cfg, i, n_min, n_max) for i in range(first, first + count)]

@@ -105,7 +105,7 @@ typedef struct ipgc_options {
                                   neighbours' colors every round (1..32; 0: default 32) */
     int32_t hub_min_degree;    /* nodes with degree above this are hubs: their conflict scans run a
                                   workgroup each, and neighbours read hub colors instead of hubs
-                                  writing them out (> light_max_degree; 0: default 4096) */
+                                  writing them out (> light_max_degree; 0: default 1024) */
     int32_t validate;          /* IPGC_VALIDATE_* */
     int32_t flags;             /* IPGC_FLAG_* */
     ipgc_profile *profile;     /* optional per-kernel timing and work counts (NULL: none) */
@@ -154,6 +154,31 @@ int ipgc_color_graph(const int32_t *csr_rowptr, const int32_t *csr_colidx, int64
 int ipgc_color_graph_ex(const int32_t *csr_rowptr, const int32_t *csr_colidx, int64_t n, int64_t m, int mode,
                         const ipgc_options *options, void *stream, int32_t *out_colors, int32_t *out_rounds,
                         ipgc_trace *trace);
+
+/*
+ * Color many graphs in one launch (the batched form of ipgc_color_graph).  The
+ * graphs run together as one disjoint union; each one gets exactly the colors
+ * and round count it gets alone.  One schedule decision is made per round for
+ * the whole batch (topology-driven iff the batch's worklist exceeds H, by
+ * default floor(6N/10) for N nodes in total).
+ *
+ * num_graphs     number of graphs G >= 0.
+ * node_off       HOST, G + 1 entries: graph g has nodes [node_off[g], node_off[g+1]) of the
+ *                packed color array; node_off[0] = 0.  Total nodes N = node_off[G] < 2^31 - 1.
+ * edge_off       HOST, G + 1 entries: graph g's column indices are colidx_packed[edge_off[g] ..
+ *                edge_off[g+1]); edge_off[0] = 0.  The total may exceed 2^31; each graph's
+ *                count must not.
+ * rowptr_packed  DEVICE, N + G int32 entries: graph g's own row pointers (n_g + 1 entries,
+ *                starting at 0 and ending at its entry count) at rowptr_packed + node_off[g] + g.
+ * colidx_packed  DEVICE, column indices local to each graph (in [0, n_g)).
+ * out_colors_packed DEVICE, N int32 entries: graph g's colors at out_colors_packed + node_off[g].
+ * out_rounds     HOST, G entries: each graph's round count (-1 for all on error).
+ * Validation, options and blocking are as for ipgc_color_graph_ex.
+ */
+int ipgc_color_graphs_batched(int64_t num_graphs, const int64_t *node_off, const int64_t *edge_off,
+                              const int32_t *rowptr_packed, const int32_t *colidx_packed, int mode,
+                              const ipgc_options *options, void *stream, int32_t *out_colors_packed,
+                              int32_t *out_rounds);
 
 /* Message for the last failing call on this thread ("" if none).  Valid until
  * the next call on the same thread. */

@@ -28,8 +28,8 @@ STATUS = {0: "IPGC_OK", -1: "IPGC_EINVAL", -2: "IPGC_ETOOBIG", -3: "IPGC_EBADCSR
           -5: "IPGC_EHIP", -6: "IPGC_ELIMIT"}
 
 # Every symbol the header declares; the tests check that the library exports all of them.
-EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_last_error", "ipgc_kernel_name", "ipgc_unit_name",
-           "ipgc_version", "ipgc_release_workspaces")
+EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_color_graphs_batched", "ipgc_last_error",
+           "ipgc_kernel_name", "ipgc_unit_name", "ipgc_version", "ipgc_release_workspaces")
 FLAG_STEPPED = 1
 PROFILE_KINDS = 16
 
@@ -91,6 +91,8 @@ def library() -> ctypes.CDLL:
         lib.ipgc_color_graph_ex.restype = i32
         lib.ipgc_color_graph_ex.argtypes = [vp, vp, i64, i64, i32, ctypes.POINTER(Options), vp, vp,
                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Trace)]
+        lib.ipgc_color_graphs_batched.restype = i32
+        lib.ipgc_color_graphs_batched.argtypes = [i64, vp, vp, vp, vp, i32, ctypes.POINTER(Options), vp, vp, vp]
         lib.ipgc_last_error.restype = ctypes.c_char_p
         lib.ipgc_last_error.argtypes = []
         lib.ipgc_kernel_name.restype = ctypes.c_char_p
@@ -201,3 +203,67 @@ def color_graph_raw(rowptr_ptr: int, colidx_ptr: int, n: int, m: int, mode: int,
                                     ctypes.c_void_p(out_ptr), ctypes.byref(rounds))
     _check(rc)
     return rounds.value
+
+
+def pack_graphs(graphs):
+    """Pack host CSR graphs [(rowptr int32[n+1], colidx int32[m]), ...] into the batched layout:
+    returns (node_off int64[G+1], edge_off int64[G+1], rowptr_packed int32[N+G],
+    colidx_packed int32[M]) as numpy arrays."""
+    import numpy as np
+
+    ns = np.array([len(rp) - 1 for rp, _ in graphs], dtype=np.int64)
+    ms = np.array([len(ci) for _, ci in graphs], dtype=np.int64)
+    node_off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    edge_off = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
+    rowptr_packed = np.concatenate([np.asarray(rp, dtype=np.int32) for rp, _ in graphs]) if graphs else \
+        np.zeros(0, dtype=np.int32)
+    colidx_packed = np.concatenate([np.asarray(ci, dtype=np.int32) for _, ci in graphs]) if graphs else \
+        np.zeros(0, dtype=np.int32)
+    return node_off, edge_off, rowptr_packed, colidx_packed
+
+
+@dataclass
+class BatchColoring:
+    colors: "object"   # torch.int32 tensor on the device: graph g's colors at node_off[g]:node_off[g+1]
+    rounds: list       # rounds per graph
+    node_off: "object"
+
+    def graph(self, g: int):
+        return self.colors[int(self.node_off[g]):int(self.node_off[g + 1])]
+
+
+def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode="hybrid", *, threshold: int = 0,
+                         light_max_degree: int = 0, hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT,
+                         stepped: bool = False, out=None, stream=None) -> BatchColoring:
+    """Color many graphs in one launch.  ``rowptr_packed`` (int32[N+G]) and ``colidx_packed``
+    (int32[M]) are device tensors in the layout of ``pack_graphs``; ``node_off`` and ``edge_off``
+    (G+1 int64 each) are host arrays.  Each graph gets the coloring and round count it gets alone."""
+    import numpy as np
+    import torch
+
+    node_off = np.ascontiguousarray(node_off, dtype=np.int64)
+    edge_off = np.ascontiguousarray(edge_off, dtype=np.int64)
+    G = len(node_off) - 1
+    N = int(node_off[-1]) if G >= 0 else 0
+    if rowptr_packed.dtype != torch.int32 or colidx_packed.dtype != torch.int32:
+        raise TypeError("rowptr_packed and colidx_packed must be int32")
+    if rowptr_packed.numel() != N + G:
+        raise ValueError("rowptr_packed needs N + G = %d entries" % (N + G))
+    if colidx_packed.numel() != int(edge_off[-1]):
+        raise ValueError("colidx_packed needs edge_off[G] entries")
+    dev = rowptr_packed.device
+    if out is None:
+        out = torch.empty(N, dtype=torch.int32, device=dev)
+    opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), int(validate),
+                   FLAG_STEPPED if stepped else 0, None)
+    rounds = np.full(max(G, 1), -1, dtype=np.int32)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    with torch.cuda.device(dev):
+        rc = library().ipgc_color_graphs_batched(
+            G, node_off.ctypes.data_as(ctypes.c_void_p), edge_off.ctypes.data_as(ctypes.c_void_p),
+            ctypes.c_void_p(rowptr_packed.data_ptr()), ctypes.c_void_p(colidx_packed.data_ptr()),
+            _mode(mode), ctypes.byref(opts), ctypes.c_void_p(stream.cuda_stream),
+            ctypes.c_void_p(out.data_ptr() if N else 0), rounds.ctypes.data_as(ctypes.c_void_p))
+    _check(rc)
+    return BatchColoring(out, rounds[:G].tolist(), node_off)

@@ -97,11 +97,12 @@ struct DBuf {
 
 struct Workspace {
     DBuf<int32_t> static_list, seg_list0, seg_list1, seg_cnt, block_cnt, trace, lstart, llen, lower;
-    DBuf<int4> hub_won;
+    DBuf<HubRec> hub_won;
     DBuf<int64_t> seg_deg, block_deg, units, trace_deg;
     DBuf<int8_t> cls;
-    DBuf<uint2> fmeta;
     DBuf<uint8_t> F;
+    DBuf<int64_t> growptr, node_off, edge_off;  // batches: union row starts, graph offsets
+    DBuf<int32_t> gbase, gidx, grounds;         // batches: per-node graph base and index, rounds per graph
     DBuf<uint64_t> ticks;
     DBuf<Barrier> bar;
     Counters *ct = nullptr;
@@ -127,7 +128,6 @@ struct Workspace {
         TRY(trace.reserve(n));
         TRY(trace_deg.reserve(n));
         TRY(cls.reserve(n));
-        TRY(fmeta.reserve(n));
         TRY(F.reserve(m + n + 64));  // word reads may run 3 bytes past the last map
         TRY(lower.reserve(m));
         TRY(lstart.reserve(n));
@@ -140,7 +140,8 @@ struct Workspace {
         static_list.release(); seg_list0.release(); seg_list1.release(); seg_cnt.release(); hub_won.release();
         block_cnt.release(); trace.release(); lstart.release(); llen.release(); lower.release();
         seg_deg.release(); block_deg.release(); units.release(); trace_deg.release(); cls.release();
-        fmeta.release(); F.release(); ticks.release(); bar.release();
+        F.release(); ticks.release(); bar.release(); growptr.release(); node_off.release(); edge_off.release();
+        gbase.release(); gidx.release(); grounds.release();
         if (ct) (void)hipFree(ct);
         if (host_ct) (void)hipHostFree(host_ct);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -203,89 +204,95 @@ int cooperative_capacity(Workspace &ws, int dev, int *out) {
         int coop = 0, cus = 0, per_cu = 0;
         HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_rounds),
-                                                             kRoundBlock, 0));
+        // the two instantiations (one graph, batches) must both fit
+        int per_cu64 = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(k_rounds<DevT<int32_t>>), kRoundBlock, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu64, reinterpret_cast<const void *>(k_rounds<DevT<int64_t>>), kRoundBlock, 0));
+        per_cu = std::min(per_cu, per_cu64);
         ws.coop_blocks = coop ? std::min(kMaxRoundBlocks, std::max(0, cus * per_cu)) : 0;
     }
     *out = ws.coop_blocks;
     return IPGC_OK;
 }
 
-int color_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t m, int mode, const ipgc_options *opt,
-               hipStream_t s, int32_t *out_colors, int32_t *out_rounds, ipgc_trace *trace) {
-    if (!out_rounds) return fail(IPGC_EINVAL, "out_rounds is NULL");
-    *out_rounds = -1;
-    if (n < 0 || m < 0) return fail(IPGC_EINVAL, "negative size (n=%lld, m=%lld)", (long long)n, (long long)m);
+// Options after validation.
+struct Params {
+    int light_max = kDefaultLightMax;
+    int hub_min = kDefaultHubMin;
+    bool check_ids = true;
+    bool stepped = false;
+    int64_t threshold = 0;  // 0: floor(6n/10) for HYBRID
+    int mode = IPGC_MODE_HYBRID;
+    ipgc_profile *prof = nullptr;
+};
+
+int parse_options(const ipgc_options *opt, int mode, Params *p) {
     if (mode != IPGC_MODE_TOPOLOGY && mode != IPGC_MODE_DATA && mode != IPGC_MODE_HYBRID)
         return fail(IPGC_EINVAL, "unknown mode %d", mode);
-    if (n >= INT32_MAX || m >= INT32_MAX)
-        return fail(IPGC_ETOOBIG, "n=%lld or m=%lld exceeds the int32 CSR", (long long)n, (long long)m);
     ipgc_options o{};
     if (opt) o = *opt;
-    const int light_max = o.light_max_degree ? o.light_max_degree : kDefaultLightMax;
-    const int hub_min = o.hub_min_degree ? o.hub_min_degree : std::max(kDefaultHubMin, light_max + 1);
-    if (light_max < 1 || light_max > kLightMaxLimit)
-        return fail(IPGC_EINVAL, "light_max_degree %d outside 1..%d", light_max, kLightMaxLimit);
-    if (hub_min <= light_max)
-        return fail(IPGC_EINVAL, "hub_min_degree %d must exceed light_max_degree %d", hub_min, light_max);
+    p->mode = mode;
+    p->light_max = o.light_max_degree ? o.light_max_degree : kDefaultLightMax;
+    p->hub_min = o.hub_min_degree ? o.hub_min_degree : std::max(kDefaultHubMin, p->light_max + 1);
+    if (p->light_max < 1 || p->light_max > kLightMaxLimit)
+        return fail(IPGC_EINVAL, "light_max_degree %d outside 1..%d", p->light_max, kLightMaxLimit);
+    if (p->hub_min <= p->light_max)
+        return fail(IPGC_EINVAL, "hub_min_degree %d must exceed light_max_degree %d", p->hub_min, p->light_max);
     if (o.validate < IPGC_VALIDATE_DEFAULT || o.validate > IPGC_VALIDATE_RANGES)
         return fail(IPGC_EINVAL, "unknown validate level %d", o.validate);
     if (o.flags & ~IPGC_FLAG_STEPPED) return fail(IPGC_EINVAL, "unknown flags 0x%x", o.flags);
-    const bool check_ids = o.validate != IPGC_VALIDATE_NONE;
-    ipgc_profile *prof = o.profile;
-    if (prof) {  // clear the out fields, keep the in fields
-        const uint32_t mask = prof->mask;
-        uint64_t *const ticks = prof->phase_ticks;
-        const int64_t cap = prof->phase_capacity;
-        std::memset(prof, 0, sizeof *prof);
-        prof->mask = mask;
-        prof->phase_ticks = ticks;
-        prof->phase_capacity = cap;
-        prof->kinds = kNumKinds;
-        prof->unit_kinds = kNumUnits;
+    p->check_ids = o.validate != IPGC_VALIDATE_NONE;
+    p->stepped = (o.flags & IPGC_FLAG_STEPPED) != 0;
+    p->threshold = o.threshold;
+    p->prof = o.profile;
+    if (p->prof) {  // clear the out fields, keep the in fields
+        ipgc_profile *pr = p->prof;
+        const uint32_t mask = pr->mask;
+        uint64_t *const ticks = pr->phase_ticks;
+        const int64_t cap = pr->phase_capacity;
+        std::memset(pr, 0, sizeof *pr);
+        pr->mask = mask;
+        pr->phase_ticks = ticks;
+        pr->phase_capacity = cap;
+        pr->kinds = kNumKinds;
+        pr->unit_kinds = kNumUnits;
     }
-    if (trace) trace->recorded = 0;
-    if (n == 0) {
-        *out_rounds = 0;
-        g_err[0] = 0;
-        return IPGC_OK;
-    }
-    if (!rowptr || !out_colors || (m > 0 && !colidx)) return fail(IPGC_EINVAL, "null device pointer");
-    int64_t H;
-    if (mode == IPGC_MODE_TOPOLOGY) H = -1;          // |WL| > -1 always holds
-    else if (mode == IPGC_MODE_DATA) H = INT64_MAX;  // never
-    else H = o.threshold > 0 ? o.threshold : (6 * n) / 10;
+    return IPGC_OK;
+}
 
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lock(g_mutex);
+Workspace &workspace(int dev) {
     if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
-    Workspace &ws = g_ws[dev];
+    return g_ws[dev];
+}
 
-    // round grid: enough workgroups for the first round, at most what is co-resident
-    int coop = 0;
-    if (!(o.flags & IPGC_FLAG_STEPPED)) TRY(cooperative_capacity(ws, dev, &coop));
+// Round grid: enough workgroups for the first round, at most what is co-resident.
+int round_grid(Workspace &ws, int dev, const Params &P, int64_t n, int *grid, int *coop) {
+    *coop = 0;
+    if (!P.stepped) TRY(cooperative_capacity(ws, dev, coop));
     const int64_t want = (n + 4 * kRoundBlock - 1) / (4 * kRoundBlock);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, coop > 0 ? coop : kMaxRoundBlocks));
+    *grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, *coop > 0 ? *coop : kMaxRoundBlocks));
+    return IPGC_OK;
+}
+
+// Everything after the input is in place: d.rowptr, d.colidx, d.c and (for a
+// batch) d.gbase / d.gidx / d.node_off / d.grounds are set by the caller.
+template <typename Off>
+int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int64_t n, int64_t m, int grid,
+        int coop, int32_t *out_rounds, ipgc_trace *trace) {
     const int64_t span = std::max<int64_t>(kPrepSpanMin, (n + kMaxPrepBlocks - 1) / kMaxPrepBlocks);
     const int prep_grid = (int)((n + span - 1) / span);
     TRY(ws.reserve(n, m, grid, prep_grid));
+    ipgc_profile *prof = P.prof;
     Profiler pf{ws, s, prof ? prof->mask : 0u, {}, 0};
 
-    // rowptr[0] == 0 and rowptr[n] == m.
-    int32_t ends[2];
-    HIP_TRY(hipMemcpyAsync(&ends[0], rowptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&ends[1], rowptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (ends[0] != 0 || ends[1] != m)
-        return fail(IPGC_EBADCSR, "rowptr[0]=%d rowptr[n]=%d, expected 0 and m=%lld", ends[0], ends[1], (long long)m);
+    int64_t H;
+    if (P.mode == IPGC_MODE_TOPOLOGY) H = -1;          // |WL| > -1 always holds
+    else if (P.mode == IPGC_MODE_DATA) H = INT64_MAX;  // never
+    else H = P.threshold > 0 ? P.threshold : (6 * n) / 10;
 
-    Dev d{};
-    d.rowptr = rowptr;
-    d.colidx = colidx;
-    d.c = out_colors;
     d.cls = ws.cls.p;
-    d.fmeta = ws.fmeta.p;
     d.F = ws.F.p;
     d.lower = ws.lower.p;
     d.lstart = ws.lstart.p;
@@ -310,9 +317,9 @@ int color_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t 
     d.tick_cap = 0;
     d.threshold = H;
     d.n = (int32_t)n;
-    d.m = (int32_t)m;
-    d.light_max = light_max;
-    d.hub_min = hub_min;
+    d.m = m;
+    d.light_max = P.light_max;
+    d.hub_min = P.hub_min;
     d.sorted = 0;
     d.grid = grid;
     if (prof && prof->phase_ticks && prof->phase_capacity > 0) {
@@ -322,22 +329,21 @@ int color_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t 
         d.tick_cap = prof->phase_capacity;
     }
 
-    HIP_TRY(hipMemsetAsync(ws.ct, 0, sizeof(Counters), s));
     HIP_TRY(hipMemsetAsync(ws.bar.p, 0, sizeof(Barrier), s));
     HIP_TRY(hipMemsetAsync(ws.units.p, 0, sizeof(int64_t) * kNumUnits * grid, s));
     HIP_TRY(hipMemsetAsync(ws.F.p, 0, (size_t)(m + n + 64), s));  // every byte map starts empty
     TRY(pf.begin(kKindInit));
-    k_init<<<prep_grid, kPrepBlock, 0, s>>>(d, ws.cls.p, ws.fmeta.p, (int32_t)span);
+    k_init<<<prep_grid, kPrepBlock, 0, s>>>(d, ws.cls.p, (int32_t)span);
     k_offsets<<<1, 1024, 0, s>>>(d, prep_grid);
     k_fill_static<<<prep_grid, kPrepBlock, 0, s>>>(d, (int32_t)span);
     TRY(pf.end(kKindInit));
     HIP_TRY(hipGetLastError());
-    // k_check reads rows through rowptr, so it only runs on row pointers that passed k_init
+    // the column checks read rows through rowptr, so they only run on row pointers that passed
     TRY(read_counters(ws, s));
     if (ws.host_ct->bad_rows) return fail(IPGC_EBADCSR, "rowptr is decreasing or outside [0, m]");
     const int64_t n_light = ws.host_ct->class_n[kL];
     const int64_t n_wide = (int64_t)ws.host_ct->class_n[kW] + ws.host_ct->class_n[kM];
-    if (check_ids && n_light > 0) {
+    if (P.check_ids && n_light > 0) {
         TRY(pf.begin(kKindCheck));
         k_check_light<<<(int)std::min<int64_t>(8192, (n_light + kPrepBlock - 1) / kPrepBlock), kPrepBlock, 0, s>>>(d);
         TRY(pf.end(kKindCheck));
@@ -349,19 +355,19 @@ int color_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t 
         TRY(pf.end(kKindPrep));
         HIP_TRY(hipGetLastError());
     }
-    if (check_ids) {
+    if (P.check_ids) {
         TRY(read_counters(ws, s));
         if (ws.host_ct->bad_ids) return fail(IPGC_EBADCSR, "a column id is outside [0, n)");
     }
-    d.sorted = check_ids && !ws.host_ct->unsorted;
+    d.sorted = P.check_ids && !ws.host_ct->unsorted;
 
     // Rounds: at most n (the worklist shrinks every round), plus the start of the one that finds it empty.
     if (coop > 0) {
         int32_t max_rounds = (int32_t)std::min<int64_t>(n + 1, INT32_MAX - 2);
         void *args[] = {&d, &max_rounds};
         TRY(pf.begin(kKindRounds));
-        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rounds), dim3(grid), dim3(kRoundBlock),
-                                           args, 0, s));
+        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rounds<DevT<Off>>), dim3(grid),
+                                           dim3(kRoundBlock), args, 0, s));
         TRY(pf.end(kKindRounds));
         TRY(read_counters(ws, s));
     } else {
@@ -410,6 +416,109 @@ int color_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t 
         prof->tick_khz = khz;
     }
     *out_rounds = rounds;
+    return IPGC_OK;
+}
+
+int color_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t m, int mode, const ipgc_options *opt,
+               hipStream_t s, int32_t *out_colors, int32_t *out_rounds, ipgc_trace *trace) {
+    if (!out_rounds) return fail(IPGC_EINVAL, "out_rounds is NULL");
+    *out_rounds = -1;
+    if (n < 0 || m < 0) return fail(IPGC_EINVAL, "negative size (n=%lld, m=%lld)", (long long)n, (long long)m);
+    if (n >= INT32_MAX || m >= INT32_MAX)
+        return fail(IPGC_ETOOBIG, "n=%lld or m=%lld exceeds the int32 CSR", (long long)n, (long long)m);
+    Params P;
+    TRY(parse_options(opt, mode, &P));
+    if (trace) trace->recorded = 0;
+    if (n == 0) {
+        *out_rounds = 0;
+        g_err[0] = 0;
+        return IPGC_OK;
+    }
+    if (!rowptr || !out_colors || (m > 0 && !colidx)) return fail(IPGC_EINVAL, "null device pointer");
+
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace &ws = workspace(dev);
+    if (!ws.ct) TRY(ws.reserve(0, 0, 1, 1));
+
+    // rowptr[0] == 0 and rowptr[n] == m.
+    int32_t ends[2];
+    HIP_TRY(hipMemcpyAsync(&ends[0], rowptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&ends[1], rowptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (ends[0] != 0 || ends[1] != m)
+        return fail(IPGC_EBADCSR, "rowptr[0]=%d rowptr[n]=%d, expected 0 and m=%lld", ends[0], ends[1], (long long)m);
+
+    int grid = 1, coop = 0;
+    TRY(round_grid(ws, dev, P, n, &grid, &coop));
+    DevT<int32_t> d{};
+    d.rowptr = rowptr;
+    d.colidx = colidx;
+    d.c = out_colors;
+    HIP_TRY(hipMemsetAsync(ws.ct, 0, sizeof(Counters), s));
+    TRY(run(ws, dev, s, P, d, n, m, grid, coop, out_rounds, trace));
+    g_err[0] = 0;
+    return IPGC_OK;
+}
+
+int batch_impl(int64_t graphs, const int64_t *node_off, const int64_t *edge_off, const int32_t *rowptr_packed,
+               const int32_t *colidx_packed, int mode, const ipgc_options *opt, hipStream_t s,
+               int32_t *out_colors_packed, int32_t *out_rounds) {
+    if (graphs < 0) return fail(IPGC_EINVAL, "negative graph count");
+    if (graphs > 0 && (!node_off || !edge_off || !out_rounds)) return fail(IPGC_EINVAL, "null host pointer");
+    for (int64_t g = 0; g < graphs; ++g) out_rounds[g] = -1;
+    if (graphs == 0) return IPGC_OK;
+    if (node_off[0] != 0 || edge_off[0] != 0) return fail(IPGC_EINVAL, "node_off[0] and edge_off[0] must be 0");
+    for (int64_t g = 0; g < graphs; ++g) {
+        const int64_t ng = node_off[g + 1] - node_off[g], mg = edge_off[g + 1] - edge_off[g];
+        if (ng < 0 || mg < 0) return fail(IPGC_EINVAL, "graph %lld has negative size", (long long)g);
+        if (mg >= INT32_MAX) return fail(IPGC_ETOOBIG, "graph %lld has %lld entries, more than int32", (long long)g, (long long)mg);
+    }
+    const int64_t n = node_off[graphs], m = edge_off[graphs];
+    if (n >= INT32_MAX) return fail(IPGC_ETOOBIG, "the batch has %lld nodes, more than int32 ids allow", (long long)n);
+    Params P;
+    TRY(parse_options(opt, mode, &P));
+    if (n == 0) {
+        for (int64_t g = 0; g < graphs; ++g) out_rounds[g] = 0;
+        g_err[0] = 0;
+        return IPGC_OK;
+    }
+    if (!rowptr_packed || !out_colors_packed || (m > 0 && !colidx_packed)) return fail(IPGC_EINVAL, "null device pointer");
+
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_mutex);
+    Workspace &ws = workspace(dev);
+    if (!ws.ct) TRY(ws.reserve(0, 0, 1, 1));
+    TRY(ws.growptr.reserve(n + 1));
+    TRY(ws.gbase.reserve(n));
+    TRY(ws.gidx.reserve(n));
+    TRY(ws.grounds.reserve(graphs));
+    TRY(ws.node_off.reserve(graphs + 1));
+    TRY(ws.edge_off.reserve(graphs + 1));
+    HIP_TRY(hipMemcpyAsync(ws.node_off.p, node_off, sizeof(int64_t) * (graphs + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(ws.edge_off.p, edge_off, sizeof(int64_t) * (graphs + 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(ws.grounds.p, 0, sizeof(int32_t) * graphs, s));
+    HIP_TRY(hipMemsetAsync(ws.ct, 0, sizeof(Counters), s));
+    k_batch_union<<<(int)std::min<int64_t>(graphs, 16384), kPrepBlock, 0, s>>>(
+        ws.node_off.p, ws.edge_off.p, rowptr_packed, graphs, ws.growptr.p, ws.gbase.p, ws.gidx.p, ws.ct);
+    HIP_TRY(hipGetLastError());
+
+    int grid = 1, coop = 0;
+    TRY(round_grid(ws, dev, P, n, &grid, &coop));
+    DevT<int64_t> d{};
+    d.rowptr = ws.growptr.p;
+    d.colidx = colidx_packed;
+    d.gbase = ws.gbase.p;
+    d.gidx = ws.gidx.p;
+    d.node_off = ws.node_off.p;
+    d.grounds = ws.grounds.p;
+    d.c = out_colors_packed;
+    int32_t rounds = -1;
+    TRY(run(ws, dev, s, P, d, n, m, grid, coop, &rounds, nullptr));
+    HIP_TRY(hipMemcpyAsync(out_rounds, ws.grounds.p, sizeof(int32_t) * graphs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     g_err[0] = 0;
     return IPGC_OK;
 }
@@ -431,13 +540,21 @@ int ipgc_color_graph_ex(const int32_t *csr_rowptr, const int32_t *csr_colidx, in
                             trace);
 }
 
+int ipgc_color_graphs_batched(int64_t num_graphs, const int64_t *node_off, const int64_t *edge_off,
+                              const int32_t *rowptr_packed, const int32_t *colidx_packed, int mode,
+                              const ipgc_options *options, void *stream, int32_t *out_colors_packed,
+                              int32_t *out_rounds) {
+    return ipgc::batch_impl(num_graphs, node_off, edge_off, rowptr_packed, colidx_packed, mode, options,
+                            (hipStream_t)stream, out_colors_packed, out_rounds);
+}
+
 const char *ipgc_last_error(void) { return ipgc::g_err; }
 
 const char *ipgc_kernel_name(int kind) { return kind >= 0 && kind < ipgc::kNumKinds ? ipgc::kKindNames[kind] : ""; }
 
 const char *ipgc_unit_name(int kind) { return kind >= 0 && kind < ipgc::kNumUnits ? ipgc::kUnitNames[kind] : ""; }
 
-int ipgc_version(void) { return (1 << 16) | 1; }
+int ipgc_version(void) { return (1 << 16) | 2; }
 
 void ipgc_release_workspaces(void) {
     std::lock_guard<std::mutex> lock(ipgc::g_mutex);

@@ -15,6 +15,16 @@
 // the node, so it never matches.  The result is the synchronous one whatever
 // the timing, with no second state array.
 //
+// Byte maps: node v owns bytes [rowptr[v] + v, rowptr[v + 1] + v] of F, one
+// per color 1..d+1; a byte is set once a neighbour has committed that color.
+//
+// A packed batch of graphs runs as one graph, the disjoint union: node ids are
+// global (each graph's first id plus the local id), row offsets are 64-bit,
+// and neighbour ids read from a row are shifted by the row owner's graph base.
+// The lower id still decides every conflict inside a graph, so each graph gets
+// exactly the coloring it gets alone; its round count is the last round in
+// which one of its nodes committed.
+//
 // Node classes by degree d:
 //   L (d <= light_max <= 32)  a thread per node.  Assign reads the row's colors
 //                             into a 64-bit mask (the answer is at most d+1);
@@ -110,13 +120,27 @@ struct Counters {
     int32_t pad[2];
 };
 
-struct Dev {
-    const int32_t *rowptr;
-    const int32_t *colidx;
+// A committed hub waiting for the push step.
+struct HubRec {
+    int64_t b, e;   // row entries
+    int32_t t;      // its color
+    int32_t base;   // first global id of its graph
+};
+
+// Everything a kernel needs, passed by value.  Off is the type of the row
+// offsets: int32_t for one graph, int64_t for a packed batch of graphs, which
+// the kernels see as one graph (the disjoint union) with global node ids.
+template <typename Off>
+struct DevT {
+    const Off *rowptr;       // row starts, n + 1 entries (a batch: union row starts)
+    const int32_t *colidx;   // column indices (a batch: ids local to each graph)
+    const int32_t *gbase;    // a batch: first global id of each node's graph (null for one graph)
+    const int32_t *gidx;     // a batch: graph index of each node (null for one graph)
+    const int64_t *node_off; // a batch: first global id of each graph, graphs + 1 entries
+    int32_t *grounds;        // a batch: rounds per graph (the last round one of its nodes committed)
     int32_t *c;              // color state (caller's output)
     const int8_t *cls;       // class per node
-    const uint2 *fmeta;      // {byte-map base, byte-map size = d+1} per node
-    uint8_t *F;              // byte maps
+    uint8_t *F;              // byte maps: node v's map is bytes [rowptr[v] + v, rowptr[v + 1] + v]
     int32_t *lower;          // ring of smaller neighbours per W/M node (region rowptr[v] .. + d)
     int32_t *lstart;         // ring start per node
     int32_t *llen;           // ring length per node
@@ -124,7 +148,7 @@ struct Dev {
     int32_t *seg_list[2];    // the two alternating segmented worklists
     int32_t *seg_cnt[2];     // [kNumClasses][grid] entries per segment
     int64_t *seg_deg[2];     // [kNumClasses][grid] degree sum per segment
-    int4 *hub_won;           // hubs committed in the current round: {node, row begin, row end, color}
+    HubRec *hub_won;         // hubs committed in the current round
     int32_t *block_cnt;      // [kNumClasses][prep grid] class counts per preparation workgroup
     int64_t *block_deg;      // [kNumClasses][prep grid]
     int64_t *units;          // [kNumUnits][grid] work counters per round workgroup
@@ -136,13 +160,31 @@ struct Dev {
     uint64_t *ticks;         // optional timeline: wall clock at each step start
     int64_t tick_cap;
     int64_t threshold;       // topology round iff |WL| > threshold
+    int64_t m;
     int32_t n;
-    int32_t m;
     int32_t light_max;
     int32_t hub_min;         // degree above which a node is class M
     int32_t sorted;          // every row strictly ascending
     int32_t grid;            // workgroups of the round kernels (segments per class)
+    int32_t pad;
+
+    // global id of a neighbour stored in row entry k of node v
+    __device__ __forceinline__ int32_t base(int32_t v) const { return gbase ? gbase[v] : 0; }
+    // one past the last valid neighbour id of node v (its graph's end)
+    __device__ __forceinline__ int64_t id_end(int32_t v) const { return gidx ? node_off[gidx[v] + 1] : n; }
 };
+
+// Byte map of node w: bytes [pos, pos + size) for colors 1..size.
+struct MapRef {
+    uint64_t pos;
+    uint32_t size;
+};
+
+template <class D>
+__device__ __forceinline__ MapRef map_of(const D &d, int32_t w) {
+    const int64_t a = d.rowptr[w], e = d.rowptr[w + 1];
+    return MapRef{(uint64_t)a + (uint64_t)w, (uint32_t)(e - a) + 1u};
+}
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -261,20 +303,20 @@ __device__ __forceinline__ int block_scan(int x, int *total) {
 // the worklist), classes, byte-map metadata, row-pointer checks, and the class
 // counts of each workgroup's node range.  Workgroup b covers nodes
 // [b*span, (b+1)*span).
-__global__ __launch_bounds__(kPrepBlock) void k_init(Dev d, int8_t *cls, uint2 *fmeta, int32_t span) {
+template <class D>
+__global__ __launch_bounds__(kPrepBlock) void k_init(D d, int8_t *cls, int32_t span) {
     const int64_t lo = (int64_t)blockIdx.x * span, hi = std::min<int64_t>(lo + span, d.n);
     int cnt[kNumClasses] = {0, 0, 0};
     int64_t deg[kNumClasses] = {0, 0, 0};
     int bad = 0;
     for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
         d.c[v] = 0;
-        const int32_t a = d.rowptr[v], e = d.rowptr[v + 1];
-        const bool b = a < 0 || e < a || e > d.m;
+        const int64_t a = d.rowptr[v], e = d.rowptr[v + 1];
+        const bool b = a < 0 || e < a || e > d.m || e - a >= INT32_MAX;
         bad |= b;
         const int64_t dv = b ? 0 : e - a;
         const int k = node_class(dv, d.light_max, d.hub_min);
         cls[v] = (int8_t)k;
-        fmeta[v] = make_uint2((uint32_t)a + (uint32_t)v, (uint32_t)dv + 1u);
         cnt[k] += 1;
         deg[k] += dv;
     }
@@ -303,7 +345,8 @@ __global__ __launch_bounds__(kPrepBlock) void k_init(Dev d, int8_t *cls, uint2 *
 
 // Prefix of the per-workgroup class counts (one workgroup): static-list
 // offsets per preparation workgroup, class sizes and regions, segment sizes.
-__global__ __launch_bounds__(1024) void k_offsets(Dev d, int32_t prep_grid) {
+template <class D>
+__global__ __launch_bounds__(1024) void k_offsets(D d, int32_t prep_grid) {
     int32_t base = 0;
     for (int k = 0; k < kNumClasses; ++k) {
         int64_t dsum = 0;
@@ -346,7 +389,8 @@ __global__ __launch_bounds__(1024) void k_offsets(Dev d, int32_t prep_grid) {
 }
 
 // The static list: every node grouped by class, ascending id within a class.
-__global__ __launch_bounds__(kPrepBlock) void k_fill_static(Dev d, int32_t span) {
+template <class D>
+__global__ __launch_bounds__(kPrepBlock) void k_fill_static(D d, int32_t span) {
     const int64_t lo = (int64_t)blockIdx.x * span, hi = std::min<int64_t>(lo + span, d.n);
     int32_t base[kNumClasses];
     for (int k = 0; k < kNumClasses; ++k) base[k] = d.block_cnt[k * gridDim.x + blockIdx.x];
@@ -365,23 +409,25 @@ __global__ __launch_bounds__(kPrepBlock) void k_fill_static(Dev d, int32_t span)
 // Column checks of light rows (a thread each, four independent loads in
 // flight): ids inside [0, n) and strictly ascending rows.  Wider rows are
 // checked by k_prep_wide while it reads them.
-__global__ __launch_bounds__(kPrepBlock) void k_check_light(Dev d) {
+template <class D>
+__global__ __launch_bounds__(kPrepBlock) void k_check_light(D d) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
     int bad = 0, unsorted = 0;
     const int32_t nL = d.ct->class_n[kL];
     const int32_t *listL = d.static_list + d.ct->static_off[kL];
     for (int64_t i = gt; i < nL; i += nt) {
         const int32_t v = listL[i];
-        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1];
-        int32_t prev = -1;
-        for (int32_t k0 = b; k0 < e; k0 += 4) {
-            int32_t u[4];
+        const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
+        const int64_t lo = d.base(v), hi = d.id_end(v);
+        int64_t prev = -1;
+        for (int64_t k0 = b; k0 < e; k0 += 4) {
+            int64_t u[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) u[j] = k0 + j < e ? d.colidx[k0 + j] : INT32_MAX;
+            for (int j = 0; j < 4; ++j) u[j] = k0 + j < e ? (int64_t)d.colidx[k0 + j] + lo : INT64_MAX;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                if (u[j] == INT32_MAX && k0 + j >= e) continue;
-                bad |= (u[j] < 0 || u[j] >= d.n);
+                if (k0 + j >= e) continue;
+                bad |= (u[j] < lo || u[j] >= hi);
                 unsorted |= (u[j] <= prev);
                 prev = u[j];
             }
@@ -398,7 +444,8 @@ __global__ __launch_bounds__(kPrepBlock) void k_check_light(Dev d) {
 // d - 1 and then reversed, so the ring starts at the W/M part and wraps around
 // into the L part, both in ascending id order: neighbours of high degree come
 // first in every scan.
-__global__ __launch_bounds__(kPrepBlock) void k_prep_wide(Dev d) {
+template <class D>
+__global__ __launch_bounds__(kPrepBlock) void k_prep_wide(D d) {
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
     const int lane = lane_id();
@@ -407,17 +454,20 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep_wide(Dev d) {
     int bad = 0, unsorted = 0;
     for (int64_t i = gw; i < nWide; i += nw) {
         const int32_t v = listWide[i];
-        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1], cap = e - b;
+        const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
+        const int32_t cap = (int32_t)(e - b);
+        const int64_t lo = d.base(v), hi = d.id_end(v);
         int32_t nl = 0, nh = 0;  // smaller neighbours of class L / of class W or M written so far
-        for (int32_t k0 = b; k0 < e; k0 += kWave) {
-            const int32_t k = k0 + lane;
+        for (int64_t k0 = b; k0 < e; k0 += kWave) {
+            const int64_t k = k0 + lane;
             int q = -1;
             int32_t u = -1;
             if (k < e) {
-                u = d.colidx[k];
-                const bool ok = u >= 0 && u < d.n;
+                const int64_t ug = (int64_t)d.colidx[k] + lo;
+                const bool ok = ug >= lo && ug < hi;
                 bad |= !ok;
-                if (k + 1 < e) unsorted |= (d.colidx[k + 1] <= u);
+                if (k + 1 < e) unsorted |= ((int64_t)d.colidx[k + 1] + lo <= ug);
+                u = (int32_t)ug;
                 if (ok && u < v) q = d.cls[u] == kL ? 0 : 1;
             }
             const uint64_t m0 = __ballot(q == 0), m1 = __ballot(q == 1);
@@ -442,6 +492,37 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep_wide(Dev d) {
     }
     if (__ballot(bad) && lane == 0) d.ct->bad_ids = 1;
     if (__ballot(unsorted) && lane == 0) d.ct->unsorted = 1;
+}
+
+// A packed batch seen as one graph: union row starts (local offsets of graph
+// g shifted by its first entry), the first global id of each node's graph,
+// and each node's graph index.  A workgroup per graph at a time; also checks
+// each graph's row pointers (local rowptr[0] == 0, rowptr[n_g] == m_g,
+// non-decreasing) and flags bad_rows.
+__global__ __launch_bounds__(kPrepBlock) void k_batch_union(const int64_t *node_off, const int64_t *edge_off,
+                                                            const int32_t *rowptr_packed, int64_t graphs,
+                                                            int64_t *growptr, int32_t *gbase, int32_t *gidx,
+                                                            Counters *ct) {
+    int bad = 0;
+    for (int64_t g = blockIdx.x; g < graphs; g += gridDim.x) {
+        const int64_t n0 = node_off[g], ng = node_off[g + 1] - n0;
+        const int64_t e0 = edge_off[g], mg = edge_off[g + 1] - e0;
+        const int32_t *rp = rowptr_packed + n0 + g;  // graph g's n_g + 1 local row pointers
+        for (int64_t lv = threadIdx.x; lv <= ng; lv += blockDim.x) {
+            const int64_t a = rp[lv];
+            if (lv == 0) bad |= a != 0;
+            if (lv == ng) bad |= a != mg;
+            if (lv < ng) {
+                const int64_t e = rp[lv + 1];
+                bad |= e < a || a < 0 || e > mg;
+                growptr[n0 + lv] = e0 + a;
+                gbase[n0 + lv] = (int32_t)n0;
+                gidx[n0 + lv] = (int32_t)g;
+            }
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) growptr[node_off[graphs]] = edge_off[graphs];
+    if (__ballot(bad) && lane_id() == 0) ct->bad_rows = 1;
 }
 
 // ============================================================== worklist views
@@ -477,7 +558,8 @@ struct RoundIn {
 
 // Load the segment counts of list `src` and build the prefix sums in shared
 // memory (all threads of the workgroup call this).
-__device__ void load_segments(const Dev &d, int src, int32_t (*pre)[kMaxRoundBlocks + 1]) {
+template <class D>
+__device__ void load_segments(const D &d, int src, int32_t (*pre)[kMaxRoundBlocks + 1]) {
     const int nb = gridDim.x;
     for (int k = 0; k < kNumClasses; ++k) {
         const int32_t x = threadIdx.x < (unsigned)nb ? d.seg_cnt[src][k * nb + threadIdx.x] : 0;
@@ -489,7 +571,8 @@ __device__ void load_segments(const Dev &d, int src, int32_t (*pre)[kMaxRoundBlo
     __syncthreads();
 }
 
-__device__ RoundIn round_view(const Dev &d, int r, int32_t (*pre)[kMaxRoundBlocks + 1]) {
+template <class D>
+__device__ RoundIn round_view(const D &d, int r, int32_t (*pre)[kMaxRoundBlocks + 1]) {
     RoundIn in;
     int32_t tot[kNumClasses];
     if (r == 1) {
@@ -523,7 +606,8 @@ struct Units {
         for (int i = 0; i < kNumUnits; ++i) u[i] = 0;
     }
     // per-workgroup totals into d.units[i][block]
-    __device__ void flush(const Dev &d) {
+    template <class D>
+    __device__ void flush(const D &d) {
         __shared__ unsigned long long s_u[kNumUnits];
         if (threadIdx.x < kNumUnits) s_u[threadIdx.x] = 0;
         __syncthreads();
@@ -554,9 +638,9 @@ struct OutSegs {
 // First zero byte of a node's byte map at or after index s (colors are the
 // index + 1).  Reads aligned 4-byte words; bytes before s and past the map end
 // count as taken.  A free byte exists: a node of degree d sees at most d colors.
-__device__ __forceinline__ int32_t first_free_word(const uint8_t *F, uint2 fm, uint32_t s, Units &un) {
-    const uint64_t end = (uint64_t)fm.x + fm.y;
-    uint64_t a = (uint64_t)fm.x + s;
+__device__ __forceinline__ int32_t first_free_word(const uint8_t *F, MapRef fm, uint32_t s, Units &un) {
+    const uint64_t end = fm.pos + fm.size;
+    uint64_t a = fm.pos + s;
     for (;;) {
         const uint64_t wa = a & ~3ull;
         uint32_t w = *reinterpret_cast<const uint32_t *>(F + wa);
@@ -567,13 +651,14 @@ __device__ __forceinline__ int32_t first_free_word(const uint8_t *F, uint2 fm, u
         const uint32_t z = (w - 0x01010101u) & ~w & 0x80808080u;
         // the lowest flagged byte is a zero byte (borrows only flag higher bytes); ffs of its
         // bit 7 is 8j + 8, so wa + j + 1 - base is the color of byte j
-        if (z) return (int32_t)(wa + (__ffs(z) >> 3) - fm.x);
+        if (z) return (int32_t)(wa + (__ffs(z) >> 3) - fm.pos);
         a = wa + 4;
-        if (a >= end) return (int32_t)fm.y;  // unreachable for a consistent map
+        if (a >= end) return (int32_t)fm.size;  // unreachable for a consistent map
     }
 }
 
-__device__ void assign_step(const Dev &d, const RoundIn &in, Units &un) {
+template <class D>
+__device__ void assign_step(const D &d, const RoundIn &in, Units &un) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
     const int64_t gw = gt / kWave, nw = nt / kWave;
     const int lane = lane_id();
@@ -582,8 +667,7 @@ __device__ void assign_step(const Dev &d, const RoundIn &in, Units &un) {
         const int32_t v = in.cv[kL].at((int32_t)i);
         const int32_t cv = d.c[v];
         if (in.topo && cv > 0) continue;
-        const uint2 fm = d.fmeta[v];
-        d.c[v] = -first_free_word(d.F, fm, cv < 0 ? (uint32_t)(-cv) - 1u : 0u, un);
+        d.c[v] = -first_free_word(d.F, map_of(d, v), cv < 0 ? (uint32_t)(-cv) - 1u : 0u, un);
         un.u[kUAssignNodes] += 1;
     }
     // classes W and M: a wavefront per node, first free byte of the byte map
@@ -592,12 +676,12 @@ __device__ void assign_step(const Dev &d, const RoundIn &in, Units &un) {
         const int32_t v = i < nW ? in.cv[kW].at((int32_t)i) : in.cv[kM].at((int32_t)(i - nW));
         const int32_t cv = d.c[v];
         if (in.topo && cv > 0) continue;
-        const uint2 fm = d.fmeta[v];
+        const MapRef fm = map_of(d, v);
         uint32_t s = cv < 0 ? (uint32_t)(-cv) - 1u : 0u;  // the previous tentative color, 0-based
-        int32_t t = (int32_t)fm.y;  // d + 1 is free if nothing smaller is
-        for (; s < fm.y; s += kWave) {
+        int32_t t = (int32_t)fm.size;  // d + 1 is free if nothing smaller is
+        for (; s < fm.size; s += kWave) {
             const uint32_t idx = s + lane;
-            const uint8_t used = idx < fm.y ? d.F[(uint64_t)fm.x + idx] : 0;
+            const uint8_t used = idx < fm.size ? d.F[fm.pos + idx] : 0;
             const uint64_t fz = __ballot(used == 0);
             un.u[kUMapBytes] += lane == 0 ? kWave : 0;
             if (fz) {
@@ -619,28 +703,31 @@ __device__ void assign_step(const Dev &d, const RoundIn &in, Units &un) {
 // the byte maps of their neighbours at once, M winners are recorded for the
 // push step; losers go to the workgroup's segment of the out list.
 
-__device__ __forceinline__ void push_color(const Dev &d, int32_t w, int32_t t) {
-    const uint2 fm = d.fmeta[w];
-    if ((uint32_t)t <= fm.y) d.F[(uint64_t)fm.x + t - 1] = 1;
+template <class D>
+__device__ __forceinline__ void push_color(const D &d, int32_t w, int32_t t) {
+    const MapRef fm = map_of(d, w);
+    if ((uint32_t)t <= fm.size) d.F[fm.pos + t - 1] = 1;
 }
 
-// Write color t into the byte maps of the neighbours in row entries [b, e),
-// one wavefront, four independent loads in flight per lane.
-__device__ __forceinline__ void push_row_wave(const Dev &d, int64_t b, int64_t e, int32_t t) {
+// Write color t into the byte maps of the neighbours in row entries [b, e)
+// (neighbour ids offset by `base`), one wavefront, four independent loads in
+// flight per lane.
+template <class D>
+__device__ __forceinline__ void push_row_wave(const D &d, int64_t b, int64_t e, int32_t t, int32_t base) {
     const int lane = lane_id();
     for (int64_t k0 = b; k0 < e; k0 += 4 * kWave) {
         int32_t w[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t k = k0 + j * kWave + lane;
-            w[j] = k < e ? d.colidx[k] : -1;
+            w[j] = k < e ? d.colidx[k] + base : -1;
         }
-        uint2 fm[4];
+        MapRef fm[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? d.fmeta[w[j]] : make_uint2(0u, 0u);
+        for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? map_of(d, w[j]) : MapRef{0, 0};
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            if ((uint32_t)t <= fm[j].y) d.F[(uint64_t)fm[j].x + t - 1] = 1;
+            if ((uint32_t)t <= fm[j].size) d.F[fm[j].pos + t - 1] = 1;
     }
 }
 
@@ -648,9 +735,11 @@ __device__ __forceinline__ void push_row_wave(const Dev &d, int64_t b, int64_t e
 // tentative color t, drops committed neighbours, keeps the others (moved to the
 // ring's end) and advances the ring start past every entry it read.  Reads at
 // least one chunk; stops after the chunk in which a conflict shows up.
-__device__ bool ring_scan_wave(const Dev &d, int32_t v, int32_t t, Units &un) {
+template <class D>
+__device__ bool ring_scan_wave(const D &d, int32_t v, int32_t t, Units &un) {
     const int lane = lane_id();
-    const int32_t base = d.rowptr[v], cap = d.rowptr[v + 1] - base;
+    const int64_t base = d.rowptr[v];
+    const int32_t cap = (int32_t)(d.rowptr[v + 1] - base);
     int32_t start = d.lstart[v], len = d.llen[v];
     int32_t read = 0, kept = 0;
     bool lose = false;
@@ -686,7 +775,8 @@ __device__ bool ring_scan_wave(const Dev &d, int32_t v, int32_t t, Units &un) {
     return lose;
 }
 
-__device__ void conflict_step(const Dev &d, const RoundIn &in, const OutSegs &os, Units &un) {
+template <class D>
+__device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, int32_t r, Units &un) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
     const int64_t gw = gt / kWave, nw = nt / kWave;
     const int lane = lane_id();
@@ -711,7 +801,7 @@ __device__ void conflict_step(const Dev &d, const RoundIn &in, const OutSegs &os
         if (in.topo && cv > 0) continue;
         const int32_t t = -cv;
         const bool lose = ring_scan_wave(d, v, t, un);
-        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1];
+        const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
         const int q = hub ? kM : kW;
         if (lane == 0) un.u[kUConflictNodes] += 1;
         if (lose) {
@@ -724,11 +814,12 @@ __device__ void conflict_step(const Dev &d, const RoundIn &in, const OutSegs &os
             if (lane == 0) {
                 d.c[v] = t;
                 un.u[kUCommits] += 1;
+                if (d.grounds) atomicMax(&d.grounds[d.gidx[v]], r);
             }
             if (hub) {
-                if (lane == 0) d.hub_won[atomicAdd(&d.ct->hub_winners, 1)] = make_int4(v, b, e, t);
+                if (lane == 0) d.hub_won[atomicAdd(&d.ct->hub_winners, 1)] = HubRec{b, e, t, d.base(v)};
             } else {
-                push_row_wave(d, b, e, t);
+                push_row_wave(d, b, e, t, d.base(v));
                 un.u[kUPushEntries] += lane == 0 ? e - b : 0;
             }
         }
@@ -739,14 +830,15 @@ __device__ void conflict_step(const Dev &d, const RoundIn &in, const OutSegs &os
         const int32_t cv = d.c[v];
         if (in.topo && cv > 0) continue;
         const int32_t t = -cv;
-        const int32_t b = d.rowptr[v], e = d.rowptr[v + 1];
+        const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
+        const int32_t gb = d.base(v);
         bool lose = false, done = false;
         int32_t read = 0;
         // four neighbours per step: their ids, then their states, then the test in row order
-        for (int32_t k0 = b; k0 < e && !lose && !done; k0 += 4) {
+        for (int64_t k0 = b; k0 < e && !lose && !done; k0 += 4) {
             int32_t u[4], cu[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) u[j] = k0 + j < e ? d.colidx[k0 + j] : INT32_MAX;
+            for (int j = 0; j < 4; ++j) u[j] = k0 + j < e ? d.colidx[k0 + j] + gb : INT32_MAX;
 #pragma unroll
             for (int j = 0; j < 4; ++j) cu[j] = u[j] < v ? d.c[u[j]] : 0;
 #pragma unroll
@@ -769,18 +861,30 @@ __device__ void conflict_step(const Dev &d, const RoundIn &in, const OutSegs &os
         } else {
             d.c[v] = t;
             un.u[kUCommits] += 1;
-            for (int32_t k0 = b; k0 < e; k0 += 4) {
+            for (int64_t k0 = b; k0 < e; k0 += 4) {
                 int32_t w[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) w[j] = k0 + j < e ? d.colidx[k0 + j] : -1;
-                uint2 fm[4];
+                for (int j = 0; j < 4; ++j) w[j] = k0 + j < e ? d.colidx[k0 + j] + gb : -1;
+                MapRef fm[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? d.fmeta[w[j]] : make_uint2(0u, 0u);
+                for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? map_of(d, w[j]) : MapRef{0, 0};
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    if ((uint32_t)t <= fm[j].y) d.F[(uint64_t)fm[j].x + t - 1] = 1;
+                    if ((uint32_t)t <= fm[j].size) d.F[fm[j].pos + t - 1] = 1;
             }
             un.u[kUPushEntries] += e - b;
+        }
+        if (d.grounds) {
+            // lanes committing nodes of the same graph as the first committing lane share one atomic
+            const bool com = !lose;
+            const int32_t g = com ? d.gidx[v] : -1;
+            const uint64_t cm = __ballot(com);
+            if (cm) {
+                const int leader = __ffsll((unsigned long long)cm) - 1;
+                const int32_t gl = __shfl(g, leader);
+                if (lane == leader) atomicMax(&d.grounds[gl], r);
+                if (com && g != gl) atomicMax(&d.grounds[g], r);
+            }
         }
     }
     __syncthreads();
@@ -794,20 +898,23 @@ __device__ void conflict_step(const Dev &d, const RoundIn &in, const OutSegs &os
 // wavefront of the grid in chunks of 256 entries.  Each workgroup stages up to
 // kRoundBlock hubs at a time (row bounds, color, chunk prefix sums) in shared
 // memory; wavefront w then takes chunks w, w + nw, ... of the staged batch.
-__device__ void hub_push_step(const Dev &d, int32_t nwon, Units &un) {
+template <class D>
+__device__ void hub_push_step(const D &d, int32_t nwon, Units &un) {
     constexpr int kChunk = 4 * kWave;
-    __shared__ int32_t s_b[kRoundBlock], s_e[kRoundBlock], s_t[kRoundBlock], s_pre[kRoundBlock + 1];
+    __shared__ int64_t s_b[kRoundBlock], s_e[kRoundBlock];
+    __shared__ int32_t s_t[kRoundBlock], s_base[kRoundBlock], s_pre[kRoundBlock + 1];
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
     for (int32_t h0 = 0; h0 < nwon; h0 += blockDim.x) {
         const int32_t h = h0 + threadIdx.x;
         int32_t chunks = 0;
         if (h < nwon) {
-            const int4 rec = d.hub_won[h];
-            s_b[threadIdx.x] = rec.y;
-            s_e[threadIdx.x] = rec.z;
-            s_t[threadIdx.x] = rec.w;
-            chunks = (rec.z - rec.y + kChunk - 1) / kChunk;
+            const HubRec rec = d.hub_won[h];
+            s_b[threadIdx.x] = rec.b;
+            s_e[threadIdx.x] = rec.e;
+            s_t[threadIdx.x] = rec.t;
+            s_base[threadIdx.x] = rec.base;
+            chunks = (int32_t)((rec.e - rec.b + kChunk - 1) / kChunk);
         }
         int total;
         const int ex = block_scan(chunks, &total);
@@ -822,8 +929,8 @@ __device__ void hub_push_step(const Dev &d, int32_t nwon, Units &un) {
                 if (s_pre[mid] <= g) lo = mid;
                 else hi = mid;
             }
-            const int64_t k0 = (int64_t)s_b[lo] + (g - s_pre[lo]) * kChunk;
-            push_row_wave(d, k0, min<int64_t>(k0 + kChunk, s_e[lo]), s_t[lo]);
+            const int64_t k0 = s_b[lo] + (g - s_pre[lo]) * kChunk;
+            push_row_wave(d, k0, min<int64_t>(k0 + kChunk, s_e[lo]), s_t[lo], s_base[lo]);
             if (lane_id() == 0) un.u[kUPushEntries] += min<int64_t>(k0 + kChunk, s_e[lo]) - k0;
         }
         __syncthreads();
@@ -834,7 +941,8 @@ __device__ void hub_push_step(const Dev &d, int32_t nwon, Units &un) {
 
 // Round bookkeeping by workgroup 0 (all its threads): trace, work units, and
 // the stop test (a round that starts with an empty worklist is not run).
-__device__ void round_record(const Dev &d, int r, const RoundIn &in, bool reset_hubs) {
+template <class D>
+__device__ void round_record(const D &d, int r, const RoundIn &in, bool reset_hubs) {
     __shared__ unsigned long long s_deg[kNumClasses];
     if (in.total == 0) {
         if (threadIdx.x == 0) {
@@ -869,7 +977,8 @@ __device__ void round_record(const Dev &d, int r, const RoundIn &in, bool reset_
     }
 }
 
-__device__ OutSegs out_segs(const Dev &d, int r) {
+template <class D>
+__device__ OutSegs out_segs(const D &d, int r) {
     OutSegs os;
     const int dst = (r + 1) & 1;  // round r writes the list round r+1 reads
     os.list = d.seg_list[dst];
@@ -882,14 +991,16 @@ __device__ OutSegs out_segs(const Dev &d, int r) {
     return os;
 }
 
-__device__ __forceinline__ void tick(const Dev &d, int64_t i) {
+template <class D>
+__device__ __forceinline__ void tick(const D &d, int64_t i) {
     if (blockIdx.x == 0 && threadIdx.x == 0 && i < d.tick_cap) d.ticks[i] = wall_clock64();
 }
 
 // Every round in one cooperative launch: assign | barrier | conflict | barrier
 // [| hub push | barrier].  Every workgroup reads the same counts after each
 // barrier, so all take the same branches and leave the loop together.
-__global__ __launch_bounds__(kRoundBlock) void k_rounds(Dev d, int32_t max_rounds) {
+template <class D>
+__global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t max_rounds) {
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
     GridBarrier gb;
     gb.setup(d.bar);
@@ -904,7 +1015,7 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(Dev d, int32_t max_round
         assign_step(d, in, un);
         gb.sync();
         tick(d, 3 * (int64_t)(r - 1) + 1);
-        conflict_step(d, in, out_segs(d, r), un);
+        conflict_step(d, in, out_segs(d, r), r, un);
         gb.sync();
         tick(d, 3 * (int64_t)(r - 1) + 2);
         // every workgroup reads the count here; it is cleared only after the next barrier
@@ -921,7 +1032,8 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(Dev d, int32_t max_round
 
 // The same steps as separate launches (the launch boundary is the barrier),
 // for hosts that cannot launch cooperatively and for per-step timing.
-__global__ __launch_bounds__(kRoundBlock) void k_assign_round(Dev d, int32_t r) {
+template <class D>
+__global__ __launch_bounds__(kRoundBlock) void k_assign_round(D d, int32_t r) {
     if (d.ct->finished) return;
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
     if (r > 1) load_segments(d, r & 1, pre);
@@ -933,18 +1045,20 @@ __global__ __launch_bounds__(kRoundBlock) void k_assign_round(Dev d, int32_t r) 
     un.flush(d);
 }
 
-__global__ __launch_bounds__(kRoundBlock) void k_conflict_round(Dev d, int32_t r) {
+template <class D>
+__global__ __launch_bounds__(kRoundBlock) void k_conflict_round(D d, int32_t r) {
     if (d.ct->finished) return;
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
     if (r > 1) load_segments(d, r & 1, pre);
     const RoundIn in = round_view(d, r, pre);
     if (in.total == 0) return;
     Units un;
-    conflict_step(d, in, out_segs(d, r), un);
+    conflict_step(d, in, out_segs(d, r), r, un);
     un.flush(d);
 }
 
-__global__ __launch_bounds__(kRoundBlock) void k_push_round(Dev d) {
+template <class D>
+__global__ __launch_bounds__(kRoundBlock) void k_push_round(D d) {
     if (d.ct->finished) return;
     const int32_t nwon = d.ct->hub_winners;
     if (nwon == 0) return;
