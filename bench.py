@@ -2,11 +2,13 @@
 """Benchmark: edges colored per second (m / time to a valid coloring) for IPGC under the hybrid
 schedule, on one MI355X.
 
-Workload (default): R-MAT scale 22, edge factor 16, (a,b,c,d) = (.57,.19,.19,.05), symmetrized,
-deduplicated, ids permuted; int32 CSR, seeded (graphgen.config_graph(2)).  m counts CSR entries,
-i.e. both directions of every edge, as the paper's edge counts do.  One step = one complete
-coloring call (validation, init, every round, result in the output buffer), with the CSR already
-resident in device memory.
+Workload (default, --config 2): R-MAT scale 22, edge factor 16, (a,b,c,d) = (.57,.19,.19,.05),
+symmetrized, deduplicated, ids permuted; int32 CSR, seeded (graphgen.config_graph(2)).  m counts
+CSR entries, i.e. both directions of every edge, as the paper's edge counts do.  One step = one
+complete coloring call (validation, init, every round, result in the output buffer), with the CSR
+already resident in device memory.  --config 1 and 3 time the other single graphs; --config 4
+times the batch of 4096 graphs (node counts log-uniform in [1e3, 1e6], half Erdos-Renyi, half
+R-MAT) colored in one batched call, with m the batch's total entry count.
 
 Printed: one JSON line with the metric, the per-schedule comparison (hybrid / data / topology),
 the roofline of the dominant kernel (algorithmic bytes from the per-unit costs times the units
@@ -89,21 +91,125 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--config", type=int, default=2, choices=[1, 2, 3],
-                   help="1: G(10000, 8); 2: R-MAT scale 22 ef 16 (default); 3: road kNN 24M nodes")
+    p.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4],
+                   help="1: G(10000, 8); 2: R-MAT scale 22 ef 16 (default); 3: road kNN 24M nodes; "
+                        "4: batch of 4096 graphs")
+    p.add_argument("--batch-graphs", type=int, default=4096, help="--config 4: number of graphs")
     p.add_argument("--mode", default="hybrid", choices=["hybrid", "data", "topology"])
     p.add_argument("--compare-steps", type=int, default=3, help="timed steps per other schedule (0: skip)")
     p.add_argument("--cpu-sample-fraction", type=float, default=0.15,
-                   help="fraction of the algorithmic bytes the CPU oracle sample covers")
+                   help="single graphs: fraction of the algorithmic bytes the CPU oracle sample covers")
+    p.add_argument("--cpu-sample-seconds", type=float, default=15.0,
+                   help="--config 4: CPU time budget of the oracle sample (whole graphs)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="also run one plain device copy of this many MiB (a reference for HBM byte counters)")
     return p.parse_args()
 
 
-def time_steps(pkg, torch, rp, ci, out, mode, steps, warmup):
+class SingleGraph:
+    """One CSR graph resident on the device."""
+
+    def __init__(self, torch, pkg, g):
+        self.torch, self.pkg, self.g = torch, pkg, g
+        self.name, self.n, self.m = g.name, g.n, g.m
+        self.rp = torch.from_numpy(g.rowptr).cuda()
+        self.ci = torch.from_numpy(g.colidx).cuda()
+        self.out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+
+    def call(self, mode, stream=None, **kw):
+        return self.pkg.color_graph(self.rp, self.ci, mode, out=self.out, stream=stream, **kw)
+
+    @staticmethod
+    def rounds(res):
+        return res.rounds
+
+    def check(self):
+        """Validity of the colors in self.out, with plain torch ops on the device."""
+        torch = self.torch
+        src = torch.repeat_interleave(torch.arange(self.n, device="cuda"), torch.diff(self.rp.long()))
+        col = self.out.long()
+        deg = torch.diff(self.rp.long())
+        valid = bool((col[src] != col[self.ci.long()]).all().item()) and bool((col >= 1).all().item()) \
+            and bool((col <= deg + 1).all().item())
+        return valid, int(col.max().item()) if self.n else 0
+
+    def cpu_baseline(self, wl, wd, fraction):
+        import numpy as np
+        import oracle
+        cum = np.cumsum(MODEL_NODE_BYTES * wl + MODEL_ENTRY_BYTES * wd)
+        k = int(np.searchsorted(cum, fraction * cum[-1]) + 1)
+        k = max(1, min(k, len(wl)))
+        frac = float(cum[k - 1] / cum[-1])
+        t = time.perf_counter()
+        oracle.color_graph(self.g.rowptr, self.g.colidx, max_rounds=k)
+        sec = time.perf_counter() - t
+        est = sec / frac
+        return {"value": self.m / est, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                "sample": "%s, first %d of %d rounds (%.1f%% of the algorithmic bytes) in %.1f s on one host core; "
+                          "full-run time extrapolated by algorithmic bytes to %.1f s" % (self.name, k, len(wl), 100 * frac, sec, est)}
+
+
+class Batch:
+    """The packed batch of graphs resident on the device (one batched call per step)."""
+
+    def __init__(self, torch, pkg, pb, name):
+        self.torch, self.pkg, self.pb = torch, pkg, pb
+        self.name, self.n, self.m = name, int(pb.node_off[-1]), int(pb.edge_off[-1])
+        self.G = pb.num_graphs
+        self.rp = torch.from_numpy(pb.rowptr_packed).cuda()
+        self.ci = torch.from_numpy(pb.colidx_packed).cuda()
+        self.out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+
+    def call(self, mode, stream=None, **kw):
+        return self.pkg.color_graphs_batched(self.rp, self.ci, self.pb.node_off, self.pb.edge_off, mode,
+                                             out=self.out, stream=stream, **kw)
+
+    @staticmethod
+    def rounds(res):
+        return max(res.rounds) if res.rounds else 0
+
+    def check(self, chunk=1 << 24):
+        """Validity of every graph's colors in self.out, by node chunks, with torch ops on the device."""
+        torch = self.torch
+        no = torch.from_numpy(self.pb.node_off).cuda()
+        eo = torch.from_numpy(self.pb.edge_off).cuda()
+        col = self.out
+        valid = True
+        for v0 in range(0, self.n, chunk):
+            v = torch.arange(v0, min(self.n, v0 + chunk), device="cuda")
+            g = torch.searchsorted(no, v, right=True) - 1
+            a = self.rp[v + g].long()
+            b = self.rp[v + g + 1].long()
+            deg = b - a
+            e0, e1 = int((eo[g[0]] + a[0]).item()), int((eo[g[-1]] + b[-1]).item())
+            src = torch.repeat_interleave(v, deg)
+            nbr = self.ci[e0:e1].long() + torch.repeat_interleave(no[g], deg)
+            c = col[v0:v0 + v.numel()].long()
+            valid &= bool((col[src] != col[nbr]).all().item()) and bool((c >= 1).all().item()) \
+                and bool((c <= deg + 1).all().item())
+            del src, nbr
+        return valid, int(col.max().item()) if self.n else 0
+
+    def cpu_baseline(self, wl, wd, seconds):
+        """The oracle over whole graphs of the batch, in index order, until the time budget is spent."""
+        import oracle
+        t = time.perf_counter()
+        done, entries = 0, 0
+        while done < self.G and time.perf_counter() - t < seconds:
+            g = self.pb.graph(done)
+            oracle.color_graph(g.rowptr, g.colidx)
+            entries += g.m
+            done += 1
+        sec = time.perf_counter() - t
+        return {"value": entries / sec, "unit": "edges/s", "cores": 1, "kind": "oracle",
+                "sample": "%s, graphs 0..%d (%d of %d graphs, %d of %d entries) colored one by one in %.1f s on one "
+                          "host core" % (self.name, done - 1, done, self.G, entries, self.m, sec)}
+
+
+def time_steps(torch, w, mode, steps, warmup):
     for _ in range(warmup):
-        pkg.color_graph(rp, ci, mode, out=out)
+        w.call(mode)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -112,7 +218,7 @@ def time_steps(pkg, torch, rp, ci, out, mode, steps, warmup):
     e0.record(stream)
     res = None
     for _ in range(steps):
-        res = pkg.color_graph(rp, ci, mode, out=out, stream=stream)
+        res = w.call(mode, stream=stream)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -140,31 +246,37 @@ def main():
         sys.exit(1)
 
     t = time.time()
-    g = gg.config_graph(args.config)
-    log("generated %s n=%d m=%d in %.1fs" % (g.name, g.n, g.m, time.time() - t))
-    rp = torch.from_numpy(g.rowptr).cuda()
-    ci = torch.from_numpy(g.colidx).cuda()
-    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    if args.config == 4:
+        pb = gg.batch_packed(4, args.batch_graphs, progress=lambda d, t: log("generated %d of %d graphs" % (d, t)))
+        name = "batch%d_er_rmat_n1e3_1e6" % args.batch_graphs
+        log("generated %s: %d graphs, N=%d M=%d in %.1fs" % (name, pb.num_graphs, pb.node_off[-1], pb.edge_off[-1],
+                                                            time.time() - t))
+        t = time.time()
+        w = Batch(torch, pkg, pb, name)
+    else:
+        g = gg.config_graph(args.config)
+        log("generated %s n=%d m=%d in %.1fs" % (g.name, g.n, g.m, time.time() - t))
+        t = time.time()
+        w = SingleGraph(torch, pkg, g)
     torch.cuda.synchronize()
+    log("uploaded in %.1fs" % (time.time() - t))
 
-    ms, wall_ms, res = time_steps(pkg, torch, rp, ci, out, args.mode, args.steps, args.warmup)
-    log("%s: %.3f ms/step (events), %.3f ms/step (wall), rounds=%d" % (args.mode, ms, wall_ms, res.rounds))
+    ms, wall_ms, res = time_steps(torch, w, args.mode, args.steps, args.warmup)
+    rounds = w.rounds(res)
+    log("%s: %.3f ms/step (events), %.3f ms/step (wall), rounds=%d" % (args.mode, ms, wall_ms, rounds))
 
-    # validity of the timed result, checked with plain torch ops on the device
-    src = torch.repeat_interleave(torch.arange(g.n, device="cuda"), torch.diff(rp.long()))
-    col = out.long()
-    valid = bool((col[src] != col[ci.long()]).all().item()) and bool((col >= 1).all().item())
-    num_colors = int(col.max().item())
+    valid, num_colors = w.check()
+    log("valid=%s colors=%d" % (valid, num_colors))
 
     # per-kernel profile and trace of one more (untimed) call
-    prof = pkg.color_graph(rp, ci, args.mode, out=out, trace=True, profile_mask=0xFFFF)
+    prof = w.call(args.mode, trace=True, profile_mask=0xFFFF)
     units = prof.profile["units"]
     work_bytes = sum(UNIT_BYTES.get(k, 0) * v for k, v in units.items())
     kinds = {}
-    for name, p in prof.profile["kernels"].items():
+    for kname, p in prof.profile["kernels"].items():
         if p["launches"] == 0:
             continue
-        kinds[name] = {"ms": round(p["ms"], 4), "launches": p["launches"], "avg_us": round(1000 * p["ms"] / p["launches"], 2)}
+        kinds[kname] = {"ms": round(p["ms"], 4), "launches": p["launches"], "avg_us": round(1000 * p["ms"] / p["launches"], 2)}
     wl = np.asarray(prof.wl_sizes, dtype=np.int64)
     wd = np.asarray(prof.wl_degrees, dtype=np.int64)
     model_bytes = int(MODEL_NODE_BYTES * wl.sum() + MODEL_ENTRY_BYTES * wd.sum())
@@ -173,7 +285,7 @@ def main():
     # the round kernel runs every round in one launch, so its per-launch units are the whole run's
     alg = model_bytes / kd["launches"] if dom == "rounds" else None
     achieved = round(alg / (kd["avg_us"] * 1e3), 1) if alg else None
-    traffic = committed_traffic(g.name) if dom == "rounds" else None
+    traffic = committed_traffic(w.name) if dom == "rounds" else None
     roofline = {"bound": "hbm", "kernel": "k_rounds" if dom == "rounds" else dom, "achieved": achieved,
                 "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4) if achieved else None, "traffic": traffic,
@@ -181,14 +293,14 @@ def main():
                 "work_bytes_per_launch": work_bytes / kd["launches"] if dom == "rounds" else None,
                 "work_GBps": round(work_bytes / kd["launches"] / (kd["avg_us"] * 1e3), 1) if dom == "rounds" else None}
 
-    modes = {args.mode: {"ms_per_step": round(ms, 3), "edges_per_s": g.m / (ms / 1000.0)}}
+    modes = {args.mode: {"ms_per_step": round(ms, 3), "edges_per_s": w.m / (ms / 1000.0)}}
     if args.compare_steps > 0:
         for other in ("hybrid", "data", "topology"):
             if other == args.mode:
                 continue
-            oms, _, ores = time_steps(pkg, torch, rp, ci, out, other, args.compare_steps, 1)
-            assert ores.rounds == res.rounds
-            modes[other] = {"ms_per_step": round(oms, 3), "edges_per_s": g.m / (oms / 1000.0)}
+            oms, _, ores = time_steps(torch, w, other, args.compare_steps, 1)
+            assert w.rounds(ores) == rounds
+            modes[other] = {"ms_per_step": round(oms, 3), "edges_per_s": w.m / (oms / 1000.0)}
             log("%s: %.3f ms/step" % (other, oms))
 
     if args.copy_mib > 0:
@@ -204,27 +316,19 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        cum = np.cumsum(MODEL_NODE_BYTES * wl + MODEL_ENTRY_BYTES * wd)
-        k = int(np.searchsorted(cum, args.cpu_sample_fraction * cum[-1]) + 1)
-        k = max(1, min(k, len(wl)))
-        frac = float(cum[k - 1] / cum[-1])
-        t = time.perf_counter()
-        oracle.color_graph(g.rowptr, g.colidx, max_rounds=k)
-        sec = time.perf_counter() - t
-        est = sec / frac
-        cpu = {"value": g.m / est, "unit": "edges/s", "cores": 1, "kind": "oracle",
-               "sample": "%s, first %d of %d rounds (%.1f%% of the algorithmic bytes) in %.1f s on one host core; "
-                         "full-run time extrapolated by algorithmic bytes to %.1f s" % (g.name, k, len(wl), 100 * frac, sec, est)}
-        log("cpu oracle sample: %d rounds in %.1fs -> %.3g edges/s" % (k, sec, cpu["value"]))
+        cpu = w.cpu_baseline(wl, wd, args.cpu_sample_seconds if args.config == 4 else args.cpu_sample_fraction)
+        log("cpu oracle: %s -> %.3g edges/s" % (cpu["sample"], cpu["value"]))
 
+    config = {"workload": w.name, "n": w.n, "m": w.m, "mode": args.mode, "rounds": rounds,
+              "colors": num_colors, "valid": valid, "parallelism": "single-gpu"}
+    if args.config == 4:
+        config["graphs"] = w.G
     line = {
         "metric": "edges colored/s (|E|/time to valid coloring), hybrid vs data-driven; p99 job latency",
-        "value": g.m / (ms / 1000.0), "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "value": w.m / (ms / 1000.0), "unit": "edges/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
-        "config": {"workload": g.name, "n": g.n, "m": g.m, "mode": args.mode, "rounds": res.rounds,
-                   "colors": num_colors, "valid": valid, "parallelism": "single-gpu"},
+        "config": config,
         "modes": modes,
         "hybrid_speedup_vs_data": round(modes["data"]["ms_per_step"] / modes["hybrid"]["ms_per_step"], 3)
         if "data" in modes and "hybrid" in modes else None,

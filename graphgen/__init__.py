@@ -38,7 +38,7 @@ def build(force: bool = False) -> str:
     """Compile gen.c into libgraphgen.so (host C, gcc, OpenMP)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -58,6 +58,14 @@ def _load():
         lib.gg_uniform_pairs.restype = None
         lib.gg_uniform_pairs.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                                          ctypes.c_uint64, _I32P, _I32P]
+        _I64P = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+        _U64P = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+        lib.gg_er_pairs.restype = ctypes.c_int64
+        lib.gg_er_pairs.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, _I32P, _I32P]
+        lib.gg_batch.restype = ctypes.c_int64
+        lib.gg_batch.argtypes = [ctypes.c_int64, _I32P, _I32P, _I64P, _U64P, _I64P, _I64P, _I64P, _I32P, _I32P, _I64P]
+        lib.gg_batch_compact.restype = None
+        lib.gg_batch_compact.argtypes = [ctypes.c_int64, _I64P, _I64P, _I32P]
         lib.gg_relabel.restype = None
         lib.gg_relabel.argtypes = [ctypes.c_int64, _I32P, _I32P]
         lib.gg_permutation.restype = None
@@ -164,32 +172,17 @@ def shuffle_rows(g: Graph, seed: int) -> tuple[np.ndarray, np.ndarray]:
 # ---------------------------------------------------------------- random families
 
 def erdos_renyi(n: int, avg_degree: float, seed_key: int, name: str = "er") -> Graph:
-    """G(n, M) with M = round(n * avg_degree / 2) distinct uniform node pairs."""
+    """G(n, M) with M = round(n * avg_degree / 2): the first M distinct unordered pairs of a
+    uniform pair stream (pair i drawn at counter 2i, self-pairs redrawn), in draw order."""
     lib = _load()
     M = int(round(n * avg_degree / 2))
     if n < 2 or M == 0:
         return from_pairs(n, [], [], name, {"n": n, "M": 0})
     M = min(M, n * (n - 1) // 2)
-    ctr = 0
-    src = np.empty(0, dtype=np.int32)
-    dst = np.empty(0, dtype=np.int32)
-    need = M
-    while True:
-        s = np.empty(need, dtype=np.int32)
-        d = np.empty(need, dtype=np.int32)
-        lib.gg_uniform_pairs(n, need, seed_key, ctr, s, d)
-        ctr += 2 * need
-        src = np.concatenate([src, s])
-        dst = np.concatenate([dst, d])
-        lo, hi = np.minimum(src, dst).astype(np.int64), np.maximum(src, dst).astype(np.int64)
-        k = lo * n + hi
-        _, first = np.unique(k, return_index=True)
-        first.sort()  # keep first occurrences in draw order
-        src, dst = src[first], dst[first]
-        if src.size >= M:
-            src, dst = src[:M], dst[:M]
-            break
-        need = M - src.size
+    src = np.empty(M, dtype=np.int32)
+    dst = np.empty(M, dtype=np.int32)
+    if lib.gg_er_pairs(n, M, seed_key, src, dst) < 0:
+        raise MemoryError("gg_er_pairs allocation failed")
     return from_pairs(n, src, dst, name, {"n": n, "M": M, "avg_degree": avg_degree})
 
 
@@ -344,3 +337,69 @@ def batch_graph(cfg: int, i: int, n_min: float = 1e3, n_max: float = 1e6) -> Gra
 def batch_graphs(cfg: int = 4, count: int = 4096, n_min: float = 1e3, n_max: float = 1e6, first: int = 0):
     """Graphs first .. first+count-1 of the batch workload (config 4: 4096 graphs, n in [1e3, 1e6])."""
     return [batch_graph(cfg, i, n_min, n_max) for i in range(first, first + count)]
+
+
+@dataclass
+class PackedBatch:
+    """Graphs in the packed layout of the batched coloring call: graph g has nodes
+    [node_off[g], node_off[g+1]) of the union, its local row pointers (n_g + 1 entries) at
+    rowptr_packed[node_off[g] + g:] and its local column ids at colidx_packed[edge_off[g]:edge_off[g+1]]."""
+    node_off: np.ndarray
+    edge_off: np.ndarray
+    rowptr_packed: np.ndarray
+    colidx_packed: np.ndarray
+    params: list
+
+    @property
+    def num_graphs(self) -> int:
+        return len(self.node_off) - 1
+
+    def graph(self, g: int) -> Graph:
+        a, b = int(self.node_off[g]), int(self.node_off[g + 1])
+        rp = self.rowptr_packed[a + g:b + g + 1].copy()
+        ci = self.colidx_packed[int(self.edge_off[g]):int(self.edge_off[g + 1])].copy()
+        return Graph(rp, ci, "batch%d" % g, dict(self.params[g]) if self.params else {})
+
+
+def batch_packed(cfg: int = 4, count: int = 4096, n_min: float = 1e3, n_max: float = 1e6, first: int = 0,
+                 progress=None) -> PackedBatch:
+    """The same graphs as batch_graphs, generated in parallel (a graph per thread) straight into
+    the packed layout.  Graph i is identical to batch_graph(cfg, i, n_min, n_max).  ``progress``,
+    if given, is called as progress(graphs_done, graphs_total) every sixteenth of the work."""
+    import math
+    lib = _load()
+    params = [batch_graph_params(cfg, i, n_min, n_max) for i in range(first, first + count)]
+    G = len(params)
+    ns = np.array([p["n"] for p in params], dtype=np.int64)
+    kind = np.array([0 if p["kind"] == "er" else 1 for p in params], dtype=np.int32)
+    scale = np.array([max(1, math.ceil(math.log2(p["n"]))) for p in params], dtype=np.int32)
+    param = np.zeros(G, dtype=np.int64)
+    cap = np.zeros(G, dtype=np.int64)
+    for g, p in enumerate(params):
+        n = p["n"]
+        if p["kind"] == "er":
+            M = int(round(n * float(p["avg_degree"]) / 2)) if n >= 2 else 0
+            param[g] = min(M, n * (n - 1) // 2)
+            cap[g] = 2 * param[g]
+        else:
+            param[g] = p["edge_factor"]
+            cap[g] = 2 * p["edge_factor"] * n
+    node_off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    cap_off = np.concatenate([[0], np.cumsum(cap)]).astype(np.int64)
+    order = np.argsort(-cap, kind="stable").astype(np.int64)
+    keys = np.array([p["key"] for p in params], dtype=np.uint64)
+    rowptr_packed = np.empty(int(node_off[-1]) + G, dtype=np.int32)
+    colidx_packed = np.empty(int(cap_off[-1]) + 1, dtype=np.int32)
+    m_out = np.zeros(G, dtype=np.int64)
+    step = max(1, (G + 15) // 16)
+    for j0 in range(0, G, step):
+        part = np.ascontiguousarray(order[j0:j0 + step])
+        rc = lib.gg_batch(part.size, kind, scale, param, keys, node_off, cap_off, part, rowptr_packed,
+                          colidx_packed, m_out)
+        if rc != 0:
+            raise MemoryError("gg_batch failed on graph %d" % (-1 - rc))
+        if progress is not None:
+            progress(min(G, j0 + step), G)
+    edge_off = np.concatenate([[0], np.cumsum(m_out)]).astype(np.int64)
+    lib.gg_batch_compact(G, cap_off, edge_off, colidx_packed)
+    return PackedBatch(node_off, edge_off, rowptr_packed, colidx_packed[:int(edge_off[-1])], params)

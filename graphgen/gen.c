@@ -19,18 +19,20 @@
 #define GOLDEN 0x9E3779B97F4A7C15ULL
 
 /* Output number `ctr` (0-based) of SplitMix64 seeded with `key`. */
-uint64_t gg_draw(uint64_t key, uint64_t ctr) {
+static inline uint64_t draw(uint64_t key, uint64_t ctr) {
     uint64_t z = key + (ctr + 1) * GOLDEN;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
     return z ^ (z >> 31);
 }
 
+uint64_t gg_draw(uint64_t key, uint64_t ctr) { return draw(key, ctr); }
+
 /* Uniform double in [0,1) from the top 53 bits of a draw. */
-static inline double unit_double(uint64_t r) { return (double)(r >> 11) * (1.0 / 9007199254740992.0); }
+static inline double unit_double(uint64_t r) { return (double)(int64_t)(r >> 11) * (1.0 / 9007199254740992.0); }
 
 /* Stream key for (a, b), e.g. (config id, graph index). */
-uint64_t gg_key(uint64_t a, uint64_t b) { return gg_draw(gg_draw(a, 0x5eed) ^ b, 0x5eed); }
+uint64_t gg_key(uint64_t a, uint64_t b) { return draw(draw(a, 0x5eed) ^ b, 0x5eed); }
 
 /* One R-MAT sample: draws (i*scale + l) for levels l = 0..scale-1; each level picks a quadrant
  * with probabilities (a, b, c, 1-a-b-c) and appends one bit to each endpoint. */
@@ -38,8 +40,10 @@ static inline void rmat_sample(int32_t scale, double a, double ab, double abc, u
                                uint64_t *pu, uint64_t *pv) {
     uint64_t u = 0, v = 0;
     for (int l = 0; l < scale; ++l) {
-        double r = unit_double(gg_draw(key, i * (uint64_t)scale + (uint64_t)l));
-        uint64_t bu = r >= ab, bv = (r >= a && r < ab) || r >= abc;
+        double r = unit_double(draw(key, i * (uint64_t)scale + (uint64_t)l));
+        /* quadrant bits without branches (the comparisons are random, so branches mispredict) */
+        const uint64_t ge_a = r >= a, ge_ab = r >= ab, ge_abc = r >= abc;
+        const uint64_t bu = ge_ab, bv = (ge_a & (ge_ab ^ 1)) | ge_abc;
         u = (u << 1) | bu;
         v = (v << 1) | bv;
     }
@@ -56,7 +60,8 @@ static inline void rmat_sample(int32_t scale, double a, double ab, double abc, u
 int64_t gg_rmat(int32_t scale, int64_t nmax, int64_t want, double a, double b, double c, uint64_t key,
                 int32_t *src, int32_t *dst) {
     const double ab = a + b, abc = a + b + c;
-    const int64_t chunk = 1 << 20;
+    int64_t chunk = 2 * want + 4096; /* the chunk size changes only the work wasted past the last sample */
+    if (chunk > (1 << 20)) chunk = 1 << 20;
     uint64_t *tu = (uint64_t *)malloc(sizeof(uint64_t) * chunk);
     uint64_t *tv = (uint64_t *)malloc(sizeof(uint64_t) * chunk);
     if (!tu || !tv) { free(tu); free(tv); return -1; }
@@ -82,8 +87,8 @@ void gg_uniform_pairs(int64_t n, int64_t count, uint64_t key, uint64_t ctr0, int
     for (int64_t i = 0; i < count; ++i) {
         uint64_t ctr = ctr0 + 2 * (uint64_t)i;
         for (;;) {
-            uint64_t u = gg_draw(key, ctr) % (uint64_t)n;
-            uint64_t v = gg_draw(key, ctr + 1) % (uint64_t)n;
+            uint64_t u = draw(key, ctr) % (uint64_t)n;
+            uint64_t v = draw(key, ctr + 1) % (uint64_t)n;
             if (u != v) { src[i] = (int32_t)u; dst[i] = (int32_t)v; break; }
             ctr += 0x100000000ULL; /* retry on a disjoint counter range */
         }
@@ -99,7 +104,7 @@ void gg_relabel(int64_t count, const int32_t *perm, int32_t *x) {
 void gg_permutation(int64_t n, uint64_t key, int32_t *perm) {
     for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
     for (int64_t i = n - 1; i > 0; --i) {
-        uint64_t j = gg_draw(key, (uint64_t)i) % (uint64_t)(i + 1);
+        uint64_t j = draw(key, (uint64_t)i) % (uint64_t)(i + 1);
         int32_t t = perm[i]; perm[i] = perm[j]; perm[j] = t;
     }
 }
@@ -167,8 +172,8 @@ int64_t gg_build_csr(int64_t n, int64_t np, const int32_t *src, const int32_t *d
 void gg_points(int64_t n, uint64_t key, double *x, double *y) {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        x[i] = unit_double(gg_draw(key, 2 * (uint64_t)i));
-        y[i] = unit_double(gg_draw(key, 2 * (uint64_t)i + 1));
+        x[i] = unit_double(draw(key, 2 * (uint64_t)i));
+        y[i] = unit_double(draw(key, 2 * (uint64_t)i + 1));
     }
 }
 
@@ -288,4 +293,186 @@ int gg_knn(int64_t n, const double *x, const double *y, const int8_t *k, int32_t
     }
     free(start); free(order); free(cellof);
     return 0;
+}
+
+/* Pair index i -> (u, v): the uniform pair gg_uniform_pairs writes for counter 2i. */
+static inline void pair_at(int64_t n, uint64_t key, uint64_t i, uint64_t *pu, uint64_t *pv) {
+    uint64_t ctr = 2 * i;
+    for (;;) {
+        uint64_t u = draw(key, ctr) % (uint64_t)n;
+        uint64_t v = draw(key, ctr + 1) % (uint64_t)n;
+        if (u != v) { *pu = u; *pv = v; return; }
+        ctr += 0x100000000ULL;
+    }
+}
+
+static inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/*
+ * G(n, M): the first M distinct unordered pairs of the uniform pair stream (pair i drawn at
+ * counter 2i, self-pairs redrawn), in draw order, via an open-addressing set of the pair keys.
+ * M must not exceed n(n-1)/2.  Returns the number of pair indices consumed, or -1.
+ */
+int64_t gg_er_pairs(int64_t n, int64_t M, uint64_t key, int32_t *src, int32_t *dst) {
+    if (M <= 0) return 0;
+    uint64_t cap = 64;
+    while (cap < 2 * (uint64_t)M) cap <<= 1;
+    uint64_t *tab = (uint64_t *)calloc(cap, sizeof(uint64_t));
+    if (!tab) return -1;
+    /* pairs are drawn PF ahead of their insertion so that their table slots can be prefetched */
+    enum { PF = 16 };
+    uint64_t ku[PF], kv[PF], kk[PF], kh[PF];
+    for (int j = 0; j < PF; ++j) {
+        pair_at(n, key, (uint64_t)j, &ku[j], &kv[j]);
+        const uint64_t lo = ku[j] < kv[j] ? ku[j] : kv[j], hi = ku[j] < kv[j] ? kv[j] : ku[j];
+        kk[j] = lo * (uint64_t)n + hi + 1; /* 0 marks an empty slot */
+        kh[j] = mix64(kk[j]) & (cap - 1);
+        __builtin_prefetch(&tab[kh[j]], 1);
+    }
+    int64_t got = 0;
+    uint64_t i = 0;
+    for (; got < M; ++i) {
+        const int j = (int)(i % PF);
+        const uint64_t u = ku[j], v = kv[j], k = kk[j];
+        uint64_t h = kh[j];
+        /* refill slot j with pair i + PF */
+        pair_at(n, key, i + PF, &ku[j], &kv[j]);
+        {
+            const uint64_t lo = ku[j] < kv[j] ? ku[j] : kv[j], hi = ku[j] < kv[j] ? kv[j] : ku[j];
+            kk[j] = lo * (uint64_t)n + hi + 1;
+            kh[j] = mix64(kk[j]) & (cap - 1);
+            __builtin_prefetch(&tab[kh[j]], 1);
+        }
+        while (tab[h] && tab[h] != k) h = (h + 1) & (cap - 1);
+        if (tab[h]) continue;
+        tab[h] = k;
+        src[got] = (int32_t)u;
+        dst[got] = (int32_t)v;
+        ++got;
+    }
+    free(tab);
+    return (int64_t)i;
+}
+
+static void sort_row(int32_t *x, int64_t len) {
+    if (len > 48) { qsort(x, (size_t)len, sizeof(int32_t), cmp_i32); return; }
+    for (int64_t i = 1; i < len; ++i) {
+        const int32_t t = x[i];
+        int64_t j = i - 1;
+        while (j >= 0 && x[j] > t) { x[j + 1] = x[j]; --j; }
+        x[j + 1] = t;
+    }
+}
+
+/* The canonical CSR of gg_build_csr, built by the calling thread alone (for one graph per
+ * thread).  colidx must hold 2*np entries; it doubles as the scatter buffer. */
+static int64_t build_csr_serial(int64_t n, int64_t np, const int32_t *src, const int32_t *dst, int32_t *rowptr,
+                                int32_t *colidx) {
+    int64_t *beg = (int64_t *)calloc((size_t)n + 2, sizeof(int64_t));
+    if (!beg) return -1;
+    for (int64_t i = 0; i < np; ++i) {
+        if (src[i] == dst[i]) continue;
+        beg[src[i] + 2]++;
+        beg[dst[i] + 2]++;
+    }
+    for (int64_t v = 0; v < n; ++v) beg[v + 2] += beg[v + 1];
+    /* beg[v + 1] is now row v's start; use it as the fill cursor, after which it is row v's end */
+    for (int64_t i = 0; i < np; ++i) {
+        if (src[i] == dst[i]) continue;
+        colidx[beg[src[i] + 1]++] = dst[i];
+        colidx[beg[dst[i] + 1]++] = src[i];
+    }
+    int64_t w = 0, b = 0;
+    rowptr[0] = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t e = beg[v + 1];
+        sort_row(colidx + b, e - b);
+        for (int64_t i = b; i < e; ++i)
+            if (i == b || colidx[i] != colidx[i - 1]) colidx[w++] = colidx[i];
+        rowptr[v + 1] = (int32_t)w;
+        b = e;
+    }
+    free(beg);
+    return w;
+}
+
+/* Whole G(n, M) graph as canonical CSR; colidx must hold 2M entries.  Returns m or -1. */
+int64_t gg_er_csr(int64_t n, int64_t M, uint64_t key, int32_t *rowptr, int32_t *colidx) {
+    int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (size_t)(M + 1));
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)(M + 1));
+    int64_t m = -1;
+    if (s && d && gg_er_pairs(n, M, key, s, d) >= 0) m = build_csr_serial(n, M, s, d, rowptr, colidx);
+    free(s); free(d);
+    return m;
+}
+
+/* Whole R-MAT graph (samples, optional seeded permutation, canonical CSR) on n <= 2^scale nodes;
+ * colidx must hold 2 * edge_factor * n entries.  Returns m or -1. */
+int64_t gg_rmat_csr(int32_t scale, int64_t n, int64_t edge_factor, double a, double b, double c, uint64_t key,
+                    int permute, int32_t *rowptr, int32_t *colidx) {
+    const int64_t want = edge_factor * n;
+    int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (size_t)(want + 1));
+    int32_t *d = (int32_t *)malloc(sizeof(int32_t) * (size_t)(want + 1));
+    int32_t *perm = permute ? (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1)) : NULL;
+    int64_t m = -1;
+    if (s && d && (perm || !permute) && gg_rmat(scale, n, want, a, b, c, key, s, d) >= 0) {
+        if (permute) {
+            gg_permutation(n, draw(key, 0xFFFFFFFFFFFFULL), perm);
+            gg_relabel(want, perm, s);
+            gg_relabel(want, perm, d);
+        }
+        m = build_csr_serial(n, want, s, d, rowptr, colidx);
+    }
+    free(s); free(d); free(perm);
+    return m;
+}
+
+/*
+ * Graphs order[0 .. count-1] of a batch, generated in parallel (one graph per thread, in the
+ * given order; pass larger graphs first).  Graph g: kind[g] 0 = G(n, M) with M = param[g], 1 =
+ * R-MAT with edge factor param[g] on scale[g]; stream key key[g].  Its local row pointers go to
+ * rowptr_packed + node_off[g] + g and its column ids to colidx_packed + cap_off[g] (room for
+ * cap_off[g+1] - cap_off[g] entries); m_out[g] receives its entry count.  Returns 0, or -1 - g
+ * for a failed graph g.
+ */
+int64_t gg_batch(int64_t count, const int32_t *kind, const int32_t *scale, const int64_t *param, const uint64_t *key,
+                 const int64_t *node_off, const int64_t *cap_off, const int64_t *order, int32_t *rowptr_packed,
+                 int32_t *colidx_packed, int64_t *m_out) {
+    int64_t fail = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < count; ++j) {
+        const int64_t g = order[j];
+        const int64_t n = node_off[g + 1] - node_off[g];
+        int32_t *rp = rowptr_packed + node_off[g] + g;
+        int32_t *ci = colidx_packed + cap_off[g];
+        int64_t m;
+        if (kind[g] == 1 && n > 0) {
+            m = gg_rmat_csr(scale[g], n, param[g], 0.57, 0.19, 0.19, key[g], 1, rp, ci);
+        } else if (kind[g] == 0 && n > 1 && param[g] > 0) {
+            m = gg_er_csr(n, param[g], key[g], rp, ci);
+        } else { /* no edges */
+            memset(rp, 0, sizeof(int32_t) * (size_t)(n + 1));
+            m = 0;
+        }
+        m_out[g] = m;
+        if (m < 0 || m > cap_off[g + 1] - cap_off[g]) {
+#pragma omp critical
+            if (!fail) fail = -1 - g;
+        }
+    }
+    return fail;
+}
+
+/* Close the gaps left by gg_batch: move graph g's entries from cap_off[g] to edge_off[g]
+ * (edge_off[g] <= cap_off[g], graphs in increasing order so nothing is overwritten early). */
+void gg_batch_compact(int64_t G, const int64_t *cap_off, const int64_t *edge_off, int32_t *colidx_packed) {
+    for (int64_t g = 0; g < G; ++g) {
+        const int64_t len = edge_off[g + 1] - edge_off[g];
+        if (len > 0 && edge_off[g] != cap_off[g])
+            memmove(colidx_packed + edge_off[g], colidx_packed + cap_off[g], sizeof(int32_t) * (size_t)len);
+    }
 }

@@ -173,12 +173,17 @@ int ipgc_color_graph_ex(const int32_t *csr_rowptr, const int32_t *csr_colidx, in
  * colidx_packed  DEVICE, column indices local to each graph (in [0, n_g)).
  * out_colors_packed DEVICE, N int32 entries: graph g's colors at out_colors_packed + node_off[g].
  * out_rounds     HOST, G entries: each graph's round count (-1 for all on error).
- * Validation, options and blocking are as for ipgc_color_graph_ex.
+ * trace          optional (NULL: none): per round of the whole batch, the size and degree sum of
+ *                the union of the graphs' worklists and the kind of round run.
+ * Every local row pointer sequence is checked (starts at 0, non-decreasing, ends at the graph's
+ * entry count) at every validation level; column ids are checked against their own graph's node
+ * count unless validation is IPGC_VALIDATE_NONE.  Options, stream and blocking are as for
+ * ipgc_color_graph_ex; the round limit is the batch's node count.
  */
 int ipgc_color_graphs_batched(int64_t num_graphs, const int64_t *node_off, const int64_t *edge_off,
                               const int32_t *rowptr_packed, const int32_t *colidx_packed, int mode,
                               const ipgc_options *options, void *stream, int32_t *out_colors_packed,
-                              int32_t *out_rounds);
+                              int32_t *out_rounds, ipgc_trace *trace);
 
 /* Message for the last failing call on this thread ("" if none).  Valid until
  * the next call on the same thread. */

@@ -92,7 +92,8 @@ def library() -> ctypes.CDLL:
         lib.ipgc_color_graph_ex.argtypes = [vp, vp, i64, i64, i32, ctypes.POINTER(Options), vp, vp,
                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Trace)]
         lib.ipgc_color_graphs_batched.restype = i32
-        lib.ipgc_color_graphs_batched.argtypes = [i64, vp, vp, vp, vp, i32, ctypes.POINTER(Options), vp, vp, vp]
+        lib.ipgc_color_graphs_batched.argtypes = [i64, vp, vp, vp, vp, i32, ctypes.POINTER(Options), vp, vp, vp,
+                                                  ctypes.POINTER(Trace)]
         lib.ipgc_last_error.restype = ctypes.c_char_p
         lib.ipgc_last_error.argtypes = []
         lib.ipgc_kernel_name.restype = ctypes.c_char_p
@@ -132,6 +133,48 @@ def _mode(mode) -> int:
     return int(mode)
 
 
+TRACE_CAPACITY = 1 << 20  # rounds recorded at most per traced call
+
+
+class _Call:
+    """Marshalled options, optional profile and optional trace of one library call."""
+
+    def __init__(self, threshold, light_max_degree, hub_min_degree, validate, stepped, trace, trace_cap,
+                 profile_mask, timeline):
+        self.prof = None
+        if profile_mask or timeline:
+            self.prof = Profile(int(profile_mask))
+            if timeline:
+                self._ticks = (ctypes.c_uint64 * int(timeline))()
+                self.prof.phase_ticks = ctypes.cast(self._ticks, ctypes.POINTER(ctypes.c_uint64))
+                self.prof.phase_capacity = int(timeline)
+        self.opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), int(validate),
+                            FLAG_STEPPED if stepped else 0,
+                            ctypes.pointer(self.prof) if self.prof is not None else None)
+        self.tr = None
+        if trace:
+            cap = max(1, min(int(trace_cap), TRACE_CAPACITY))
+            self._wl = (ctypes.c_int32 * cap)()
+            self._wd = (ctypes.c_int64 * cap)()
+            self._topo = (ctypes.c_int8 * cap)()
+            self.tr = Trace(cap, ctypes.cast(self._wl, ctypes.POINTER(ctypes.c_int32)),
+                            ctypes.cast(self._wd, ctypes.POINTER(ctypes.c_int64)),
+                            ctypes.cast(self._topo, ctypes.POINTER(ctypes.c_int8)), 0)
+
+    def trace_ref(self):
+        return ctypes.byref(self.tr) if self.tr is not None else None
+
+    def finish(self, res):
+        if self.tr is not None:
+            k = self.tr.recorded
+            res.wl_sizes = list(self._wl[:k])
+            res.wl_degrees = list(self._wd[:k])
+            res.topology = list(self._topo[:k])
+        if self.prof is not None:
+            res.profile = self.prof.as_dict()
+        return res
+
+
 def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_degree: int = 0,
                 hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT, stepped: bool = False, out=None,
                 stream=None, trace: bool = False, profile_mask: int = 0, timeline: int = 0) -> Coloring:
@@ -158,42 +201,17 @@ def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_
         out = torch.empty(n, dtype=torch.int32, device=rowptr.device)
     elif out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() or out.device != rowptr.device:
         raise ValueError("out must be a contiguous int32 tensor of n entries on the graph's device")
-    prof = None
-    if profile_mask or timeline:
-        prof = Profile(int(profile_mask))
-        if timeline:
-            ticks = (ctypes.c_uint64 * int(timeline))()
-            prof.phase_ticks = ctypes.cast(ticks, ctypes.POINTER(ctypes.c_uint64))
-            prof.phase_capacity = int(timeline)
-    opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), int(validate),
-                   FLAG_STEPPED if stepped else 0, ctypes.pointer(prof) if prof is not None else None)
+    call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, n, profile_mask, timeline)
     rounds = ctypes.c_int32(-1)
-    tr = None
-    if trace:
-        cap = max(n, 1)
-        wl = (ctypes.c_int32 * cap)()
-        wd = (ctypes.c_int64 * cap)()
-        topo = (ctypes.c_int8 * cap)()
-        tr = Trace(cap, ctypes.cast(wl, ctypes.POINTER(ctypes.c_int32)), ctypes.cast(wd, ctypes.POINTER(ctypes.c_int64)),
-                   ctypes.cast(topo, ctypes.POINTER(ctypes.c_int8)), 0)
     if stream is None:
         stream = torch.cuda.current_stream(rowptr.device)
     with torch.cuda.device(rowptr.device):
         rc = library().ipgc_color_graph_ex(
             ctypes.c_void_p(rowptr.data_ptr()), ctypes.c_void_p(colidx.data_ptr() if m else 0), n, m,
-            _mode(mode), ctypes.byref(opts), ctypes.c_void_p(stream.cuda_stream),
-            ctypes.c_void_p(out.data_ptr() if n else 0), ctypes.byref(rounds),
-            ctypes.byref(tr) if tr is not None else None)
+            _mode(mode), ctypes.byref(call.opts), ctypes.c_void_p(stream.cuda_stream),
+            ctypes.c_void_p(out.data_ptr() if n else 0), ctypes.byref(rounds), call.trace_ref())
     _check(rc)
-    res = Coloring(out, rounds.value)
-    if tr is not None:
-        k = tr.recorded
-        res.wl_sizes = list(wl[:k])
-        res.wl_degrees = list(wd[:k])
-        res.topology = list(topo[:k])
-    if prof is not None:
-        res.profile = prof.as_dict()
-    return res
+    return call.finish(Coloring(out, rounds.value))
 
 
 def color_graph_raw(rowptr_ptr: int, colidx_ptr: int, n: int, m: int, mode: int, out_ptr: int) -> int:
@@ -227,6 +245,10 @@ class BatchColoring:
     colors: "object"   # torch.int32 tensor on the device: graph g's colors at node_off[g]:node_off[g+1]
     rounds: list       # rounds per graph
     node_off: "object"
+    wl_sizes: list | None = None    # per round of the batch: size of the union of the worklists
+    wl_degrees: list | None = None  # per round of the batch: degree sum over that union
+    topology: list | None = None
+    profile: dict | None = None
 
     def graph(self, g: int):
         return self.colors[int(self.node_off[g]):int(self.node_off[g + 1])]
@@ -234,10 +256,12 @@ class BatchColoring:
 
 def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode="hybrid", *, threshold: int = 0,
                          light_max_degree: int = 0, hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT,
-                         stepped: bool = False, out=None, stream=None) -> BatchColoring:
+                         stepped: bool = False, out=None, stream=None, trace: bool = False,
+                         profile_mask: int = 0) -> BatchColoring:
     """Color many graphs in one launch.  ``rowptr_packed`` (int32[N+G]) and ``colidx_packed``
     (int32[M]) are device tensors in the layout of ``pack_graphs``; ``node_off`` and ``edge_off``
-    (G+1 int64 each) are host arrays.  Each graph gets the coloring and round count it gets alone."""
+    (G+1 int64 each) are host arrays.  Each graph gets the coloring and round count it gets alone.
+    ``trace`` and ``profile_mask`` are as for ``color_graph``, over the rounds of the whole batch."""
     import numpy as np
     import torch
 
@@ -247,15 +271,20 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
     N = int(node_off[-1]) if G >= 0 else 0
     if rowptr_packed.dtype != torch.int32 or colidx_packed.dtype != torch.int32:
         raise TypeError("rowptr_packed and colidx_packed must be int32")
+    if not (rowptr_packed.is_cuda and colidx_packed.is_cuda):
+        raise ValueError("rowptr_packed and colidx_packed must be device tensors")
     if rowptr_packed.numel() != N + G:
         raise ValueError("rowptr_packed needs N + G = %d entries" % (N + G))
     if colidx_packed.numel() != int(edge_off[-1]):
         raise ValueError("colidx_packed needs edge_off[G] entries")
+    rowptr_packed = rowptr_packed.contiguous()
+    colidx_packed = colidx_packed.contiguous()
     dev = rowptr_packed.device
     if out is None:
         out = torch.empty(N, dtype=torch.int32, device=dev)
-    opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), int(validate),
-                   FLAG_STEPPED if stepped else 0, None)
+    elif out.dtype != torch.int32 or out.numel() != N or not out.is_contiguous() or out.device != dev:
+        raise ValueError("out must be a contiguous int32 tensor of N entries on the batch's device")
+    call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, N, profile_mask, 0)
     rounds = np.full(max(G, 1), -1, dtype=np.int32)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
@@ -263,7 +292,7 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
         rc = library().ipgc_color_graphs_batched(
             G, node_off.ctypes.data_as(ctypes.c_void_p), edge_off.ctypes.data_as(ctypes.c_void_p),
             ctypes.c_void_p(rowptr_packed.data_ptr()), ctypes.c_void_p(colidx_packed.data_ptr()),
-            _mode(mode), ctypes.byref(opts), ctypes.c_void_p(stream.cuda_stream),
-            ctypes.c_void_p(out.data_ptr() if N else 0), rounds.ctypes.data_as(ctypes.c_void_p))
+            _mode(mode), ctypes.byref(call.opts), ctypes.c_void_p(stream.cuda_stream),
+            ctypes.c_void_p(out.data_ptr() if N else 0), rounds.ctypes.data_as(ctypes.c_void_p), call.trace_ref())
     _check(rc)
-    return BatchColoring(out, rounds[:G].tolist(), node_off)
+    return call.finish(BatchColoring(out, rounds[:G].tolist(), node_off))

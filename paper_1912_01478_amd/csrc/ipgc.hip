@@ -464,7 +464,7 @@ int color_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t 
 
 int batch_impl(int64_t graphs, const int64_t *node_off, const int64_t *edge_off, const int32_t *rowptr_packed,
                const int32_t *colidx_packed, int mode, const ipgc_options *opt, hipStream_t s,
-               int32_t *out_colors_packed, int32_t *out_rounds) {
+               int32_t *out_colors_packed, int32_t *out_rounds, ipgc_trace *trace) {
     if (graphs < 0) return fail(IPGC_EINVAL, "negative graph count");
     if (graphs > 0 && (!node_off || !edge_off || !out_rounds)) return fail(IPGC_EINVAL, "null host pointer");
     for (int64_t g = 0; g < graphs; ++g) out_rounds[g] = -1;
@@ -516,7 +516,7 @@ int batch_impl(int64_t graphs, const int64_t *node_off, const int64_t *edge_off,
     d.grounds = ws.grounds.p;
     d.c = out_colors_packed;
     int32_t rounds = -1;
-    TRY(run(ws, dev, s, P, d, n, m, grid, coop, &rounds, nullptr));
+    TRY(run(ws, dev, s, P, d, n, m, grid, coop, &rounds, trace));
     HIP_TRY(hipMemcpyAsync(out_rounds, ws.grounds.p, sizeof(int32_t) * graphs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     g_err[0] = 0;
@@ -543,9 +543,9 @@ int ipgc_color_graph_ex(const int32_t *csr_rowptr, const int32_t *csr_colidx, in
 int ipgc_color_graphs_batched(int64_t num_graphs, const int64_t *node_off, const int64_t *edge_off,
                               const int32_t *rowptr_packed, const int32_t *colidx_packed, int mode,
                               const ipgc_options *options, void *stream, int32_t *out_colors_packed,
-                              int32_t *out_rounds) {
+                              int32_t *out_rounds, ipgc_trace *trace) {
     return ipgc::batch_impl(num_graphs, node_off, edge_off, rowptr_packed, colidx_packed, mode, options,
-                            (hipStream_t)stream, out_colors_packed, out_rounds);
+                            (hipStream_t)stream, out_colors_packed, out_rounds, trace);
 }
 
 const char *ipgc_last_error(void) { return ipgc::g_err; }
@@ -554,7 +554,7 @@ const char *ipgc_kernel_name(int kind) { return kind >= 0 && kind < ipgc::kNumKi
 
 const char *ipgc_unit_name(int kind) { return kind >= 0 && kind < ipgc::kNumUnits ? ipgc::kUnitNames[kind] : ""; }
 
-int ipgc_version(void) { return (1 << 16) | 2; }
+int ipgc_version(void) { return (1 << 16) | 3; }
 
 void ipgc_release_workspaces(void) {
     std::lock_guard<std::mutex> lock(ipgc::g_mutex);

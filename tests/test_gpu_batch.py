@@ -193,3 +193,66 @@ def test_batch_errors():
     for g, (col, rounds) in zip(graphs, out):
         ref = oracle.color_graph(g.rowptr, g.colidx)
         assert rounds == ref.rounds and (col == ref.colors).all()
+
+
+def _check_packed_on_device(pb, rp, ci, col, chunk=1 << 24):
+    """Every graph's coloring is proper, 1 <= c[v] <= deg(v) + 1, checked by node chunks on the device."""
+    no = torch.from_numpy(pb.node_off).cuda()
+    eo = torch.from_numpy(pb.edge_off).cuda()
+    n = int(pb.node_off[-1])
+    for v0 in range(0, n, chunk):
+        v = torch.arange(v0, min(n, v0 + chunk), device="cuda")
+        g = torch.searchsorted(no, v, right=True) - 1
+        a = rp[v + g].long()
+        b = rp[v + g + 1].long()
+        deg = b - a
+        e0, e1 = int((eo[g[0]] + a[0]).item()), int((eo[g[-1]] + b[-1]).item())
+        src = torch.repeat_interleave(v, deg)
+        nbr = ci[e0:e1].long() + torch.repeat_interleave(no[g], deg)
+        assert bool((col[src] != col[nbr]).all().item()), "improper coloring in nodes %d.." % v0
+        c = col[v0:v0 + v.numel()].long()
+        assert bool((c >= 1).all().item()) and bool((c <= deg + 1).all().item())
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1500)
+def test_batch_workload_full_size():
+    """The batch workload at full size: 4096 graphs with n log-uniform in [1e3, 1e6] (about 5.9e8
+    nodes and 1.1e10 entries), colored in one batched call as bench.py --config 4 times it.  Every
+    graph is checked for a proper coloring on the device; a sample (the smallest Erdos-Renyi and
+    R-MAT graphs, two mid-sized ones and the largest graph) is compared with the oracle exactly,
+    and all three schedules must agree everywhere."""
+    import time
+    import paper_1912_01478_amd as ip
+    t = time.time()
+    pb = gg.batch_packed(4, 4096, progress=lambda d, t: print("[gpu batch full] generated %d of %d" % (d, t), flush=True))
+    print("[gpu batch full] generated N=%d M=%d in %.0fs" % (pb.node_off[-1], pb.edge_off[-1], time.time() - t),
+          flush=True)
+    rp = torch.from_numpy(pb.rowptr_packed).cuda()
+    ci = torch.from_numpy(pb.colidx_packed).cuda()
+    res = ip.color_graphs_batched(rp, ci, pb.node_off, pb.edge_off, "hybrid")
+    torch.cuda.synchronize()
+    print("[gpu batch full] hybrid done, max rounds %d" % max(res.rounds), flush=True)
+    _check_packed_on_device(pb, rp, ci, res.colors)
+    ns = np.diff(pb.node_off)
+    assert all(r >= 1 for r in res.rounds)
+    kinds = np.array([p["kind"] == "er" for p in pb.params])
+    sample = {int(np.argmin(np.where(kinds, ns, 1 << 40))), int(np.argmin(np.where(~kinds, ns, 1 << 40))),
+              int(np.argmax(ns))}
+    mid = np.nonzero((ns > 50_000) & (ns < 100_000))[0]
+    sample |= set(int(x) for x in mid[:2])
+    col = res.colors
+    for g in sorted(sample):
+        gr = pb.graph(g)
+        ref = oracle.color_graph(gr.rowptr, gr.colidx)
+        print("[gpu batch full] oracle graph %d n=%d m=%d rounds=%d" % (g, gr.n, gr.m, ref.rounds), flush=True)
+        assert res.rounds[g] == ref.rounds
+        assert (res.graph(g).cpu().numpy() == ref.colors).all()
+    for mode in ("data", "topology"):
+        other = ip.color_graphs_batched(rp, ci, pb.node_off, pb.edge_off, mode)
+        torch.cuda.synchronize()
+        assert other.rounds == res.rounds and torch.equal(other.colors, col), mode
+        del other
+    del rp, ci, res, col
+    torch.cuda.empty_cache()
+    ip.library().ipgc_release_workspaces()
