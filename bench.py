@@ -95,7 +95,12 @@ def parse():
                    help="1: G(10000, 8); 2: R-MAT scale 22 ef 16 (default); 3: road kNN 24M nodes; "
                         "4: batch of 4096 graphs")
     p.add_argument("--batch-graphs", type=int, default=4096, help="--config 4: number of graphs")
-    p.add_argument("--mode", default="hybrid", choices=["hybrid", "data", "topology"])
+    p.add_argument("--mode", default=None, choices=["hybrid", "data", "topology"],
+                   help="round schedule (default: the tuned one for the workload's class, else hybrid)")
+    p.add_argument("--tune-table", default=None, help="JSON table of tuned options (default: the package's)")
+    p.add_argument("--autotune", action="store_true", help="tune the options on this workload first and store them")
+    p.add_argument("--no-tuning", action="store_true", help="use the library's default options")
+    p.add_argument("--tune-steps", type=int, default=3, help="--autotune: timed calls per candidate")
     p.add_argument("--compare-steps", type=int, default=3, help="timed steps per other schedule (0: skip)")
     p.add_argument("--cpu-sample-fraction", type=float, default=0.15,
                    help="single graphs: fraction of the algorithmic bytes the CPU oracle sample covers")
@@ -117,8 +122,11 @@ class SingleGraph:
         self.ci = torch.from_numpy(g.colidx).cuda()
         self.out = torch.empty(g.n, dtype=torch.int32, device="cuda")
 
-    def call(self, mode, stream=None, **kw):
-        return self.pkg.color_graph(self.rp, self.ci, mode, out=self.out, stream=stream, **kw)
+    def call(self, stream=None, **kw):
+        return self.pkg.color_graph(self.rp, self.ci, out=self.out, stream=stream, **kw)
+
+    def features(self):
+        return self.pkg.autotune.graph_features(self.g.rowptr)
 
     @staticmethod
     def rounds(res):
@@ -161,9 +169,12 @@ class Batch:
         self.ci = torch.from_numpy(pb.colidx_packed).cuda()
         self.out = torch.empty(self.n, dtype=torch.int32, device="cuda")
 
-    def call(self, mode, stream=None, **kw):
-        return self.pkg.color_graphs_batched(self.rp, self.ci, self.pb.node_off, self.pb.edge_off, mode,
+    def call(self, stream=None, **kw):
+        return self.pkg.color_graphs_batched(self.rp, self.ci, self.pb.node_off, self.pb.edge_off,
                                              out=self.out, stream=stream, **kw)
+
+    def features(self):
+        return self.pkg.autotune.graph_features(self.pb.rowptr_packed, self.pb.node_off)
 
     @staticmethod
     def rounds(res):
@@ -207,9 +218,9 @@ class Batch:
                           "host core" % (self.name, done - 1, done, self.G, entries, self.m, sec)}
 
 
-def time_steps(torch, w, mode, steps, warmup):
+def time_steps(torch, w, kw, steps, warmup):
     for _ in range(warmup):
-        w.call(mode)
+        w.call(**kw)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -218,7 +229,7 @@ def time_steps(torch, w, mode, steps, warmup):
     e0.record(stream)
     res = None
     for _ in range(steps):
-        res = w.call(mode, stream=stream)
+        res = w.call(stream=stream, **kw)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -261,15 +272,32 @@ def main():
     torch.cuda.synchronize()
     log("uploaded in %.1fs" % (time.time() - t))
 
-    ms, wall_ms, res = time_steps(torch, w, args.mode, args.steps, args.warmup)
+    from paper_1912_01478_amd import autotune as at
+    table_path = args.tune_table or at.DEFAULT_TABLE
+    table = at.TuneTable.load(table_path)
+    feats = w.features()
+    if args.autotune:
+        choice, tms, dms, trials = at.tune(lambda s, **kw: w.call(stream=s, **kw), w.n, steps=args.tune_steps, log=log)
+        key = table.put(feats, choice, tms, dms, w.name, trials)
+        table.save(table_path)
+        log("tuned %s: %s %.3f ms (defaults %.3f ms) -> %s" % (key, choice, tms, dms, table_path))
+    choice = None if args.no_tuning else table.lookup(feats)
+    tuned = dict(at.DEFAULT if choice is None else choice)
+    if args.mode:
+        tuned["schedule"] = args.mode
+    kw = at.call_kwargs(tuned, w.n)
+    mode = kw["mode"]
+    log("options (%s, class %s): %s" % ("tuned" if choice else "defaults", at.class_key(feats), kw))
+
+    ms, wall_ms, res = time_steps(torch, w, kw, args.steps, args.warmup)
     rounds = w.rounds(res)
-    log("%s: %.3f ms/step (events), %.3f ms/step (wall), rounds=%d" % (args.mode, ms, wall_ms, rounds))
+    log("%s: %.3f ms/step (events), %.3f ms/step (wall), rounds=%d" % (mode, ms, wall_ms, rounds))
 
     valid, num_colors = w.check()
     log("valid=%s colors=%d" % (valid, num_colors))
 
     # per-kernel profile and trace of one more (untimed) call
-    prof = w.call(args.mode, trace=True, profile_mask=0xFFFF)
+    prof = w.call(trace=True, profile_mask=0xFFFF, **kw)
     units = prof.profile["units"]
     work_bytes = sum(UNIT_BYTES.get(k, 0) * v for k, v in units.items())
     kinds = {}
@@ -293,15 +321,19 @@ def main():
                 "work_bytes_per_launch": work_bytes / kd["launches"] if dom == "rounds" else None,
                 "work_GBps": round(work_bytes / kd["launches"] / (kd["avg_us"] * 1e3), 1) if dom == "rounds" else None}
 
-    modes = {args.mode: {"ms_per_step": round(ms, 3), "edges_per_s": w.m / (ms / 1000.0)}}
+    modes = {}
     if args.compare_steps > 0:
+        # each schedule with the other options as chosen (and, if tuned, the library defaults)
         for other in ("hybrid", "data", "topology"):
-            if other == args.mode:
-                continue
-            oms, _, ores = time_steps(torch, w, other, args.compare_steps, 1)
+            okw = dict(kw, mode=other, threshold=0)
+            oms, _, ores = time_steps(torch, w, okw, args.compare_steps, 1)
             assert w.rounds(ores) == rounds
             modes[other] = {"ms_per_step": round(oms, 3), "edges_per_s": w.m / (oms / 1000.0)}
             log("%s: %.3f ms/step" % (other, oms))
+        if choice is not None:
+            dms, _, _ = time_steps(torch, w, at.call_kwargs(at.DEFAULT, w.n), args.compare_steps, 1)
+            modes["defaults"] = {"ms_per_step": round(dms, 3), "edges_per_s": w.m / (dms / 1000.0)}
+            log("library defaults: %.3f ms/step" % dms)
 
     if args.copy_mib > 0:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counter readings calibrate the
@@ -319,8 +351,10 @@ def main():
         cpu = w.cpu_baseline(wl, wd, args.cpu_sample_seconds if args.config == 4 else args.cpu_sample_fraction)
         log("cpu oracle: %s -> %.3g edges/s" % (cpu["sample"], cpu["value"]))
 
-    config = {"workload": w.name, "n": w.n, "m": w.m, "mode": args.mode, "rounds": rounds,
-              "colors": num_colors, "valid": valid, "parallelism": "single-gpu"}
+    config = {"workload": w.name, "n": w.n, "m": w.m, "mode": mode, "rounds": rounds,
+              "colors": num_colors, "valid": valid, "parallelism": "single-gpu",
+              "options": {k: v for k, v in kw.items() if k != "mode"}, "tuning_class": at.class_key(feats),
+              "tuned": choice is not None}
     if args.config == 4:
         config["graphs"] = w.G
     line = {

@@ -109,6 +109,9 @@ typedef struct ipgc_options {
     int32_t validate;          /* IPGC_VALIDATE_* */
     int32_t flags;             /* IPGC_FLAG_* */
     ipgc_profile *profile;     /* optional per-kernel timing and work counts (NULL: none) */
+    int32_t workgroups;        /* workgroups of the round kernels (0: one per 4096 nodes, at most what
+                                  the device keeps resident at once; larger values are clamped to that) */
+    int32_t reserved;          /* must be 0 */
 } ipgc_options;
 
 /* Option flags. */

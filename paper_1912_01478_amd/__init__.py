@@ -65,7 +65,8 @@ class Options(ctypes.Structure):
     """Mirror of ``ipgc_options``."""
     _fields_ = [("threshold", ctypes.c_int64), ("light_max_degree", ctypes.c_int32),
                 ("hub_min_degree", ctypes.c_int32), ("validate", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("profile", ctypes.POINTER(Profile))]
+                ("flags", ctypes.c_int32), ("profile", ctypes.POINTER(Profile)), ("workgroups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Trace(ctypes.Structure):
@@ -140,7 +141,7 @@ class _Call:
     """Marshalled options, optional profile and optional trace of one library call."""
 
     def __init__(self, threshold, light_max_degree, hub_min_degree, validate, stepped, trace, trace_cap,
-                 profile_mask, timeline):
+                 profile_mask, timeline, workgroups=0):
         self.prof = None
         if profile_mask or timeline:
             self.prof = Profile(int(profile_mask))
@@ -150,7 +151,7 @@ class _Call:
                 self.prof.phase_capacity = int(timeline)
         self.opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), int(validate),
                             FLAG_STEPPED if stepped else 0,
-                            ctypes.pointer(self.prof) if self.prof is not None else None)
+                            ctypes.pointer(self.prof) if self.prof is not None else None, int(workgroups), 0)
         self.tr = None
         if trace:
             cap = max(1, min(int(trace_cap), TRACE_CAPACITY))
@@ -177,14 +178,16 @@ class _Call:
 
 def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_degree: int = 0,
                 hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT, stepped: bool = False, out=None,
-                stream=None, trace: bool = False, profile_mask: int = 0, timeline: int = 0) -> Coloring:
+                stream=None, trace: bool = False, profile_mask: int = 0, timeline: int = 0,
+                workgroups: int = 0) -> Coloring:
     """Color the symmetric CSR graph (``rowptr``: int32[n+1], ``colidx``: int32[m], both on the
     HIP device) and return the 1-based colors and round count.  ``mode`` is "topology", "data"
     or "hybrid"; ``threshold`` is H for hybrid rounds (0: floor(6n/10)).  ``stepped`` runs one
     launch per round step instead of one cooperative launch.  Options only change the time,
     never the result.  ``trace`` returns the per-round worklist sizes and degree sums;
     ``profile_mask`` times the selected kernel kinds with HIP events (bit k = kind k); ``timeline``
-    > 0 records that many device wall-clock ticks at the round-step boundaries."""
+    > 0 records that many device wall-clock ticks at the round-step boundaries; ``workgroups`` sets
+    the round kernels' workgroup count (0: automatic)."""
     import torch
 
     if rowptr.dtype != torch.int32 or colidx.dtype != torch.int32:
@@ -201,7 +204,8 @@ def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_
         out = torch.empty(n, dtype=torch.int32, device=rowptr.device)
     elif out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() or out.device != rowptr.device:
         raise ValueError("out must be a contiguous int32 tensor of n entries on the graph's device")
-    call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, n, profile_mask, timeline)
+    call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, n, profile_mask, timeline,
+                 workgroups)
     rounds = ctypes.c_int32(-1)
     if stream is None:
         stream = torch.cuda.current_stream(rowptr.device)
@@ -257,7 +261,7 @@ class BatchColoring:
 def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode="hybrid", *, threshold: int = 0,
                          light_max_degree: int = 0, hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT,
                          stepped: bool = False, out=None, stream=None, trace: bool = False,
-                         profile_mask: int = 0) -> BatchColoring:
+                         profile_mask: int = 0, workgroups: int = 0) -> BatchColoring:
     """Color many graphs in one launch.  ``rowptr_packed`` (int32[N+G]) and ``colidx_packed``
     (int32[M]) are device tensors in the layout of ``pack_graphs``; ``node_off`` and ``edge_off``
     (G+1 int64 each) are host arrays.  Each graph gets the coloring and round count it gets alone.
@@ -284,7 +288,7 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
         out = torch.empty(N, dtype=torch.int32, device=dev)
     elif out.dtype != torch.int32 or out.numel() != N or not out.is_contiguous() or out.device != dev:
         raise ValueError("out must be a contiguous int32 tensor of N entries on the batch's device")
-    call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, N, profile_mask, 0)
+    call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, N, profile_mask, 0, workgroups)
     rounds = np.full(max(G, 1), -1, dtype=np.int32)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
@@ -296,3 +300,6 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
             ctypes.c_void_p(out.data_ptr() if N else 0), rounds.ctypes.data_as(ctypes.c_void_p), call.trace_ref())
     _check(rc)
     return call.finish(BatchColoring(out, rounds[:G].tolist(), node_off))
+
+
+from . import autotune  # noqa: E402  (options search; imports nothing heavy at load time)

@@ -224,6 +224,7 @@ struct Params {
     bool check_ids = true;
     bool stepped = false;
     int64_t threshold = 0;  // 0: floor(6n/10) for HYBRID
+    int workgroups = 0;     // 0: automatic
     int mode = IPGC_MODE_HYBRID;
     ipgc_profile *prof = nullptr;
 };
@@ -243,6 +244,9 @@ int parse_options(const ipgc_options *opt, int mode, Params *p) {
     if (o.validate < IPGC_VALIDATE_DEFAULT || o.validate > IPGC_VALIDATE_RANGES)
         return fail(IPGC_EINVAL, "unknown validate level %d", o.validate);
     if (o.flags & ~IPGC_FLAG_STEPPED) return fail(IPGC_EINVAL, "unknown flags 0x%x", o.flags);
+    if (o.workgroups < 0) return fail(IPGC_EINVAL, "negative workgroups %d", o.workgroups);
+    if (o.reserved != 0) return fail(IPGC_EINVAL, "reserved option field must be 0");
+    p->workgroups = o.workgroups;
     p->check_ids = o.validate != IPGC_VALIDATE_NONE;
     p->stepped = (o.flags & IPGC_FLAG_STEPPED) != 0;
     p->threshold = o.threshold;
@@ -271,7 +275,7 @@ Workspace &workspace(int dev) {
 int round_grid(Workspace &ws, int dev, const Params &P, int64_t n, int *grid, int *coop) {
     *coop = 0;
     if (!P.stepped) TRY(cooperative_capacity(ws, dev, coop));
-    const int64_t want = (n + 4 * kRoundBlock - 1) / (4 * kRoundBlock);
+    const int64_t want = P.workgroups > 0 ? P.workgroups : (n + 4 * kRoundBlock - 1) / (4 * kRoundBlock);
     *grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, *coop > 0 ? *coop : kMaxRoundBlocks));
     return IPGC_OK;
 }
@@ -554,7 +558,7 @@ const char *ipgc_kernel_name(int kind) { return kind >= 0 && kind < ipgc::kNumKi
 
 const char *ipgc_unit_name(int kind) { return kind >= 0 && kind < ipgc::kNumUnits ? ipgc::kUnitNames[kind] : ""; }
 
-int ipgc_version(void) { return (1 << 16) | 3; }
+int ipgc_version(void) { return (1 << 16) | 4; }
 
 void ipgc_release_workspaces(void) {
     std::lock_guard<std::mutex> lock(ipgc::g_mutex);

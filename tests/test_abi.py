@@ -45,7 +45,7 @@ def test_version(lib):
 
 def test_struct_layouts():
     import paper_1912_01478_amd as pkg
-    assert ctypes.sizeof(pkg.Options) == 32
+    assert ctypes.sizeof(pkg.Options) == 40
     assert ctypes.sizeof(pkg.Trace) == 40
     assert ctypes.sizeof(pkg.Profile) == 8 + 8 * 16 * 2 + 8 + 8 * 16 + 32
 
