@@ -91,9 +91,9 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4],
+    p.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
                    help="1: G(10000, 8); 2: R-MAT scale 22 ef 16 (default); 3: road kNN 24M nodes; "
-                        "4: batch of 4096 graphs")
+                        "4: batch of 4096 graphs; 5: serving stream")
     p.add_argument("--batch-graphs", type=int, default=4096, help="--config 4: number of graphs")
     p.add_argument("--mode", default=None, choices=["hybrid", "data", "topology"],
                    help="round schedule (default: the tuned one for the workload's class, else hybrid)")
@@ -107,6 +107,10 @@ def parse():
     p.add_argument("--cpu-sample-seconds", type=float, default=15.0,
                    help="--config 4: CPU time budget of the oracle sample (whole graphs)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--jobs", type=int, default=2000, help="--config 5: jobs per run")
+    p.add_argument("--budget-gb", type=float, default=64.0, help="--config 5: device memory of the server arena")
+    p.add_argument("--rounds-per-step", type=int, default=8, help="--config 5: rounds per server step")
+    p.add_argument("--loads", default="0.5,0.8", help="--config 5: arrival rates as fractions of the saturated rate")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="also run one plain device copy of this many MiB (a reference for HBM byte counters)")
     return p.parse_args()
@@ -236,6 +240,91 @@ def time_steps(torch, w, kw, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall * 1000.0 / steps, res
 
 
+def serve(pkg, pb, arrivals, args, avg_degree):
+    """Runs the job stream through one server: job g is submitted at arrivals[g] seconds after the
+    start (its host CSR is a view of the packed arrays).  Returns (wall seconds, latencies, stats)."""
+    import numpy as np
+    J = pb.num_graphs
+    nodes, edges = pkg.Server.capacity_for(int(args.budget_gb * (1 << 30)), avg_degree)
+    srv = pkg.Server(nodes, edges, max_jobs=4096, rounds_per_step=args.rounds_per_step)
+    views = []
+    for g in range(J):
+        a, b = int(pb.node_off[g]), int(pb.node_off[g + 1])
+        views.append((pb.rowptr_packed[a + g:b + g + 1], pb.colidx_packed[int(pb.edge_off[g]):int(pb.edge_off[g + 1])]))
+    lat = np.full(J, np.nan)
+    ids = {}
+    nxt, done = 0, 0
+    last_log = 0.0
+    t0 = time.perf_counter()
+    while done < J:
+        now = time.perf_counter() - t0
+        while nxt < J and arrivals[nxt] <= now:
+            ids[srv.submit(*views[nxt])] = nxt
+            nxt += 1
+        if len(ids) > done:
+            srv.step()
+        elif nxt < J:
+            time.sleep(max(0.0, min(arrivals[nxt] - now, 0.01)))
+        t = time.perf_counter() - t0
+        for r in srv.poll():
+            if r.status != 0:
+                raise RuntimeError("job %d failed with status %d" % (r.job_id, r.status))
+            g = ids[r.job_id]
+            lat[g] = t - arrivals[g]
+            done += 1
+        if t - last_log > 20.0:
+            log("serving: %d of %d jobs done at %.1fs" % (done, J, t))
+            last_log = t
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return wall, lat, st
+
+
+def main_serving(args, pkg, gg, np):
+    t = time.time()
+    pb = gg.serving_jobs(5, args.jobs, progress=lambda d, tot: log("generated %d of %d jobs" % (d, tot)))
+    J, M = pb.num_graphs, int(pb.edge_off[-1])
+    avg_degree = M / max(1, int(pb.node_off[-1]))
+    log("generated %d jobs, N=%d M=%d in %.1fs" % (J, pb.node_off[-1], M, time.time() - t))
+    runs = {}
+    wall, lat, st = serve(pkg, pb, np.zeros(J), args, avg_degree)
+    sat_jobs = J / wall
+    runs["saturated"] = {"jobs_per_s": sat_jobs, "edges_per_s": M / wall, "wall_s": wall,
+                         "p50_ms": 1000 * float(np.percentile(lat, 50)), "p99_ms": 1000 * float(np.percentile(lat, 99)),
+                         "peak_resident": st["peak_resident"], "rounds": st["rounds"], "steps": st["steps"]}
+    log("saturated: %.1f jobs/s, %.3g edges/s, wall %.2fs" % (sat_jobs, M / wall, wall))
+    rng = np.random.Generator(np.random.PCG64(5))
+    gaps = rng.exponential(1.0, size=J)
+    for load in [float(x) for x in args.loads.split(",") if x]:
+        lam = load * sat_jobs
+        arrivals = np.cumsum(gaps) / lam
+        arrivals -= arrivals[0]
+        wall, lat, st = serve(pkg, pb, arrivals, args, avg_degree)
+        runs["load_%.2f" % load] = {
+            "arrival_rate_jobs_per_s": lam, "jobs_per_s": J / wall, "edges_per_s": M / wall, "wall_s": wall,
+            "p50_ms": 1000 * float(np.percentile(lat, 50)), "p99_ms": 1000 * float(np.percentile(lat, 99)),
+            "peak_resident": st["peak_resident"], "rounds": st["rounds"], "steps": st["steps"]}
+        log("load %.2f (%.1f jobs/s): p50 %.1f ms p99 %.1f ms" % (load, lam, runs["load_%.2f" % load]["p50_ms"],
+                                                                  runs["load_%.2f" % load]["p99_ms"]))
+    key = "load_%.2f" % max(float(x) for x in args.loads.split(",")) if args.loads else "saturated"
+    head = runs.get(key, runs["saturated"])
+    nodes, edges = pkg.Server.capacity_for(int(args.budget_gb * (1 << 30)), avg_degree)
+    line = {
+        "metric": "edges colored/s (|E|/time to valid coloring), hybrid vs data-driven; p99 job latency",
+        "value": head["edges_per_s"], "unit": "edges/s", "n_gpus": 1, "steps": J, "warmup": 0,
+        "ms_per_step": round(1000 * head["wall_s"] / J, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "serving_%djobs_c4mix_10pct_rmat_s20" % J, "jobs": J, "n": int(pb.node_off[-1]), "m": M,
+                   "budget_gb": args.budget_gb, "arena_nodes": nodes, "arena_edges": edges,
+                   "rounds_per_step": args.rounds_per_step, "mode": "hybrid", "parallelism": "single-gpu",
+                   "headline_run": key},
+        "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+        "runs": runs, "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -256,6 +345,8 @@ def main():
         print("bench.py: no HIP device", file=sys.stderr)
         sys.exit(1)
 
+    if args.config == 5:
+        return main_serving(args, pkg, gg, np)
     t = time.time()
     if args.config == 4:
         pb = gg.batch_packed(4, args.batch_graphs, progress=lambda d, t: log("generated %d of %d graphs" % (d, t)))

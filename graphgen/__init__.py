@@ -366,9 +366,38 @@ def batch_packed(cfg: int = 4, count: int = 4096, n_min: float = 1e3, n_max: flo
     """The same graphs as batch_graphs, generated in parallel (a graph per thread) straight into
     the packed layout.  Graph i is identical to batch_graph(cfg, i, n_min, n_max).  ``progress``,
     if given, is called as progress(graphs_done, graphs_total) every sixteenth of the work."""
+    params = [batch_graph_params(cfg, i, n_min, n_max) for i in range(first, first + count)]
+    return pack_params(params, progress)
+
+
+def serving_job_params(cfg: int, i: int, big_fraction: float = 0.1, big_scale: int = 20, big_ef: int = 16) -> dict:
+    """Job i of the serving stream: with probability big_fraction an R-MAT graph of scale big_scale
+    (n = 2^big_scale) and edge factor big_ef, else a graph drawn as in the batch workload."""
+    k = key(cfg, i)
+    u = _unit(int(_load().gg_draw(k, 0x5E7)), 0)
+    if u < big_fraction:
+        return {"kind": "rmat", "n": 1 << big_scale, "edge_factor": big_ef, "key": k}
+    return batch_graph_params(cfg, i)
+
+
+def serving_jobs(cfg: int = 5, count: int = 2000, big_fraction: float = 0.1, progress=None) -> PackedBatch:
+    """The jobs of the serving stream, packed like a batch (job i is graph i)."""
+    return pack_params([serving_job_params(cfg, i, big_fraction) for i in range(count)], progress)
+
+
+def params_graph(p: dict) -> Graph:
+    """The graph of one parameter record (as batch_graph builds it)."""
+    import math
+    if p["kind"] == "er":
+        return erdos_renyi(p["n"], float(p["avg_degree"]), p["key"])
+    return rmat(max(1, math.ceil(math.log2(p["n"]))), p["edge_factor"], p["key"], n=p["n"])
+
+
+def pack_params(params: list, progress=None) -> PackedBatch:
+    """Generate the graphs of `params` (records as from batch_graph_params) in parallel into the
+    packed layout."""
     import math
     lib = _load()
-    params = [batch_graph_params(cfg, i, n_min, n_max) for i in range(first, first + count)]
     G = len(params)
     ns = np.array([p["n"] for p in params], dtype=np.int64)
     kind = np.array([0 if p["kind"] == "er" else 1 for p in params], dtype=np.int32)

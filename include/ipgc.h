@@ -188,6 +188,93 @@ int ipgc_color_graphs_batched(int64_t num_graphs, const int64_t *node_off, const
                               const ipgc_options *options, void *stream, int32_t *out_colors_packed,
                               int32_t *out_rounds, ipgc_trace *trace);
 
+/*
+ * Serving: a device-resident job server with continuous batching.
+ *
+ * A server owns a device arena sized once at creation: node slots, CSR entry
+ * slots, byte-map bytes and job slots.  Submitted jobs wait in a FIFO queue
+ * until the arena has room for them (memory admission); an admitted job's CSR,
+ * color state, byte maps and rings stay resident until it completes.  Each
+ * ipgc_server_step runs up to rounds_per_step rounds of IPGC over every
+ * resident job at once (one cooperative launch, the jobs forming one disjoint
+ * union), after retiring the jobs that completed and admitting queued jobs
+ * that now fit.  Jobs that arrive while others are running join at the next
+ * step, so their rounds overlap on the device with those of the jobs already
+ * resident.  Every job gets exactly the colors and round count it gets alone
+ * (the rules of ipgc_color_graph make each job's result independent of
+ * everything else in the union).  The schedule of each round (topology-driven
+ * iff the union's worklist exceeds H, by default floor(6 N / 10) for the N
+ * resident nodes) changes only the time.
+ *
+ * A server is used from one thread at a time and runs on the device that was
+ * current at creation.
+ */
+typedef struct ipgc_server ipgc_server;
+
+typedef struct ipgc_server_config {
+    int64_t node_capacity;    /* arena node slots; a job takes n + 1 */
+    int64_t edge_capacity;    /* arena CSR entry slots; a job takes m */
+    int32_t max_jobs;         /* jobs resident at once (job slots) */
+    int32_t rounds_per_step;  /* rounds per ipgc_server_step (0: 8) */
+    int32_t mode;             /* ipgc_mode of the rounds */
+    int32_t reserved;         /* must be 0 */
+    ipgc_options options;     /* threshold (0: floor(6N/10) over the resident nodes), light_max_degree,
+                                 hub_min_degree, workgroups; validate must not be IPGC_VALIDATE_NONE
+                                 (every admitted job is checked); flags and profile must be 0 */
+} ipgc_server_config;
+
+/* Outcome of a finished job. */
+typedef struct ipgc_job_result {
+    int64_t job_id;
+    int32_t status;   /* IPGC_OK, or IPGC_EBADCSR if the job's CSR failed the checks */
+    int32_t rounds;   /* the job's round count (-1 on error) */
+} ipgc_job_result;
+
+typedef struct ipgc_server_stats {
+    int64_t steps;          /* ipgc_server_step calls that ran rounds */
+    int64_t rounds;         /* rounds run (over the union) */
+    int64_t submitted, admitted, completed;
+    int64_t resident;       /* jobs resident now */
+    int64_t queued;         /* jobs waiting for room */
+    int64_t resident_nodes; /* nodes of the resident jobs */
+    int64_t resident_edges; /* CSR entries of the resident jobs */
+    int64_t peak_resident;  /* most jobs resident at once */
+    int64_t arena_bytes;    /* device memory held by the server */
+    int64_t units[IPGC_PROFILE_KINDS]; /* work units summed over all rounds (see ipgc_unit_name) */
+} ipgc_server_stats;
+
+/* Creates a server and allocates its arena on the current device.  Fails with
+ * IPGC_ENOMEM if the arena does not fit, IPGC_EINVAL for a bad config. */
+int ipgc_server_create(const ipgc_server_config *config, ipgc_server **out);
+
+/*
+ * Queues a job.  rowptr (n + 1 int32) and colidx (m int32, ids in [0, n)) are
+ * HOST pointers in the CSR format of ipgc_color_graph; out_colors is a HOST
+ * array of n int32 that receives the colors when the job completes.  All three
+ * must stay valid until ipgc_server_poll reports the job.  IPGC_ETOOBIG if the
+ * job can never fit the arena; IPGC_EINVAL for negative sizes or null
+ * pointers.  job_id receives the job's id (ids count up from 0).
+ */
+int ipgc_server_submit(ipgc_server *server, const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t m,
+                       int32_t *out_colors, int64_t *job_id);
+
+/* One step: retire completed jobs (their colors are copied to out_colors),
+ * admit queued jobs in FIFO order while they fit, then run up to
+ * rounds_per_step rounds over the resident jobs.  Blocks until the rounds are
+ * done.  Does nothing if no job is resident or queued. */
+int ipgc_server_step(ipgc_server *server);
+
+/* Results of the jobs finished since the last poll, oldest first: up to
+ * capacity entries go to results, their number to count.  A job finishes
+ * during the step after the one in which its last node committed, or at once
+ * if it failed its checks or has no nodes. */
+int ipgc_server_poll(ipgc_server *server, ipgc_job_result *results, int64_t capacity, int64_t *count);
+
+int ipgc_server_stats_get(const ipgc_server *server, ipgc_server_stats *stats);
+
+/* Frees the arena.  Queued and resident jobs are dropped. */
+void ipgc_server_destroy(ipgc_server *server);
+
 /* Message for the last failing call on this thread ("" if none).  Valid until
  * the next call on the same thread. */
 const char *ipgc_last_error(void);

@@ -29,7 +29,9 @@ STATUS = {0: "IPGC_OK", -1: "IPGC_EINVAL", -2: "IPGC_ETOOBIG", -3: "IPGC_EBADCSR
 
 # Every symbol the header declares; the tests check that the library exports all of them.
 EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_color_graphs_batched", "ipgc_last_error",
-           "ipgc_kernel_name", "ipgc_unit_name", "ipgc_version", "ipgc_release_workspaces")
+           "ipgc_kernel_name", "ipgc_unit_name", "ipgc_version", "ipgc_release_workspaces", "ipgc_server_create",
+           "ipgc_server_submit", "ipgc_server_step", "ipgc_server_poll", "ipgc_server_stats_get",
+           "ipgc_server_destroy")
 FLAG_STEPPED = 1
 PROFILE_KINDS = 16
 
@@ -69,6 +71,25 @@ class Options(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class ServerConfig(ctypes.Structure):
+    """Mirror of ``ipgc_server_config``."""
+    _fields_ = [("node_capacity", ctypes.c_int64), ("edge_capacity", ctypes.c_int64), ("max_jobs", ctypes.c_int32),
+                ("rounds_per_step", ctypes.c_int32), ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("options", Options)]
+
+
+class JobResult(ctypes.Structure):
+    """Mirror of ``ipgc_job_result``."""
+    _fields_ = [("job_id", ctypes.c_int64), ("status", ctypes.c_int32), ("rounds", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    """Mirror of ``ipgc_server_stats``."""
+    _fields_ = [(k, ctypes.c_int64) for k in ("steps", "rounds", "submitted", "admitted", "completed", "resident",
+                                              "queued", "resident_nodes", "resident_edges", "peak_resident",
+                                              "arena_bytes")] + [("units", ctypes.c_int64 * 16)]
+
+
 class Trace(ctypes.Structure):
     """Mirror of ``ipgc_trace``."""
     _fields_ = [("capacity", ctypes.c_int64), ("wl_size", ctypes.POINTER(ctypes.c_int32)),
@@ -95,6 +116,19 @@ def library() -> ctypes.CDLL:
         lib.ipgc_color_graphs_batched.restype = i32
         lib.ipgc_color_graphs_batched.argtypes = [i64, vp, vp, vp, vp, i32, ctypes.POINTER(Options), vp, vp, vp,
                                                   ctypes.POINTER(Trace)]
+        srv = ctypes.c_void_p
+        lib.ipgc_server_create.restype = i32
+        lib.ipgc_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(srv)]
+        lib.ipgc_server_submit.restype = i32
+        lib.ipgc_server_submit.argtypes = [srv, vp, vp, i64, i64, vp, ctypes.POINTER(ctypes.c_int64)]
+        lib.ipgc_server_step.restype = i32
+        lib.ipgc_server_step.argtypes = [srv]
+        lib.ipgc_server_poll.restype = i32
+        lib.ipgc_server_poll.argtypes = [srv, ctypes.POINTER(JobResult), i64, ctypes.POINTER(ctypes.c_int64)]
+        lib.ipgc_server_stats_get.restype = i32
+        lib.ipgc_server_stats_get.argtypes = [srv, ctypes.POINTER(ServerStats)]
+        lib.ipgc_server_destroy.restype = None
+        lib.ipgc_server_destroy.argtypes = [srv]
         lib.ipgc_last_error.restype = ctypes.c_char_p
         lib.ipgc_last_error.argtypes = []
         lib.ipgc_kernel_name.restype = ctypes.c_char_p
@@ -300,6 +334,101 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
             ctypes.c_void_p(out.data_ptr() if N else 0), rounds.ctypes.data_as(ctypes.c_void_p), call.trace_ref())
     _check(rc)
     return call.finish(BatchColoring(out, rounds[:G].tolist(), node_off))
+
+
+# ---------------------------------------------------------------- serving
+
+# Device bytes per arena node slot and per CSR entry slot of a server (see ipgc_server_create):
+# per node: row start 8, graph base/index 8, state 4, class 1, ring start/length 8, static list 4,
+# staging 4, both segmented lists 24; per entry: column id 4, ring 4, byte map 1.
+SERVER_NODE_BYTES = 61
+SERVER_ENTRY_BYTES = 9
+
+
+@dataclass
+class JobDone:
+    job_id: int
+    status: int        # 0, or a negative ipgc_status
+    rounds: int
+    colors: "object"   # numpy int32 array of the job's colors (None on error)
+
+
+class Server:
+    """A device-resident job server with continuous batching (``ipgc_server_*``).  Jobs are host
+    CSR arrays; ``step()`` admits queued jobs that fit, runs ``rounds_per_step`` rounds over every
+    resident job and retires finished ones; ``poll()`` returns the finished jobs."""
+
+    def __init__(self, node_capacity: int, edge_capacity: int, max_jobs: int = 4096, rounds_per_step: int = 0,
+                 mode="hybrid", threshold: int = 0, light_max_degree: int = 0, hub_min_degree: int = 0,
+                 workgroups: int = 0):
+        import numpy as np  # noqa: F401
+        opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), VALIDATE_DEFAULT, 0, None,
+                       int(workgroups), 0)
+        cfg = ServerConfig(int(node_capacity), int(edge_capacity), int(max_jobs), int(rounds_per_step), _mode(mode),
+                           0, opts)
+        self._h = ctypes.c_void_p()
+        _check(library().ipgc_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+        self._jobs = {}  # job id -> (rowptr, colidx, out) kept alive until the job is polled
+
+    @staticmethod
+    def capacity_for(budget_bytes: int, avg_degree: float):
+        """Node and entry capacities that fill about budget_bytes for jobs of the given average degree."""
+        nodes = int(budget_bytes / (SERVER_NODE_BYTES + SERVER_ENTRY_BYTES * avg_degree))
+        return nodes, int(nodes * avg_degree)
+
+    def submit(self, rowptr, colidx) -> int:
+        import numpy as np
+        rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+        ci = np.ascontiguousarray(colidx, dtype=np.int32)
+        n = rp.size - 1
+        out = np.empty(max(n, 0), dtype=np.int32)
+        jid = ctypes.c_int64(-1)
+        _check(library().ipgc_server_submit(self._h, rp.ctypes.data_as(ctypes.c_void_p),
+                                            ci.ctypes.data_as(ctypes.c_void_p), n, ci.size,
+                                            out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(jid)))
+        self._jobs[jid.value] = (rp, ci, out)
+        return jid.value
+
+    def step(self) -> None:
+        _check(library().ipgc_server_step(self._h))
+
+    def poll(self) -> list:
+        res = (JobResult * 256)()
+        out = []
+        while True:
+            cnt = ctypes.c_int64(0)
+            _check(library().ipgc_server_poll(self._h, res, 256, ctypes.byref(cnt)))
+            for i in range(cnt.value):
+                r = res[i]
+                _, _, colors = self._jobs.pop(r.job_id)
+                out.append(JobDone(r.job_id, r.status, r.rounds, colors if r.status == 0 else None))
+            if cnt.value < 256:
+                return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(library().ipgc_server_stats_get(self._h, ctypes.byref(st)))
+        d = {k: getattr(st, k) for k, _ in ServerStats._fields_ if k != "units"}
+        d["units"] = {library().ipgc_unit_name(k).decode(): st.units[k] for k in range(16)
+                      if library().ipgc_unit_name(k)}
+        return d
+
+    def close(self) -> None:
+        if self._h:
+            library().ipgc_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 from . import autotune  # noqa: E402  (options search; imports nothing heavy at load time)

@@ -30,14 +30,9 @@
 
 #include "ipgc.h"
 #include "ipgc_device.hpp"
+#include "ipgc_host.hpp"
 
 namespace ipgc {
-namespace {
-
-constexpr int kDefaultLightMax = 32;
-constexpr int kDefaultHubMin = 1024;
-constexpr int kPrepSpanMin = 2048;  // nodes per preparation workgroup (at least)
-constexpr int kMaxPrepBlocks = 65536;
 
 thread_local char g_err[512];
 
@@ -49,51 +44,16 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-#define HIP_TRY(expr)                                                                              \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) return fail(IPGC_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
+namespace {
 
-#define TRY(expr)             \
-    do {                      \
-        int rc_ = (expr);     \
-        if (rc_) return rc_;  \
-    } while (0)
+constexpr int kPrepSpanMin = 2048;  // nodes per preparation workgroup (at least)
+constexpr int kMaxPrepBlocks = 65536;
 
 // Profile kernel kinds.
 enum Kind { kKindInit = 0, kKindCheck, kKindPrep, kKindRounds, kKindAssign, kKindConflict, kKindPush, kNumKinds };
 const char *const kKindNames[kNumKinds] = {"init", "check", "prep", "rounds", "assign_step", "conflict_step", "push_step"};
 const char *const kUnitNames[kNumUnits] = {"assign_nodes",   "pull_entries", "map_bytes",    "conflict_nodes",
                                            "conflict_entries", "list_writes", "push_entries", "commits"};
-
-template <typename T>
-int grow(T **p, int64_t *cap, int64_t want) {
-    if (want <= *cap) return IPGC_OK;
-    if (*p) (void)hipFree(*p);
-    *p = nullptr;
-    *cap = 0;
-    const int64_t alloc = std::max<int64_t>(want, 1024);
-    if (hipMalloc(p, sizeof(T) * alloc) != hipSuccess) {
-        (void)hipGetLastError();
-        *p = nullptr;
-        return fail(IPGC_ENOMEM, "device allocation of %lld bytes failed", (long long)(sizeof(T) * alloc));
-    }
-    *cap = alloc;
-    return IPGC_OK;
-}
-
-template <typename T>
-struct DBuf {
-    T *p = nullptr;
-    int64_t cap = 0;
-    int reserve(int64_t n) { return grow(&p, &cap, n); }
-    void release() {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        cap = 0;
-    }
-};
 
 struct Workspace {
     DBuf<int32_t> static_list, seg_list0, seg_list1, seg_cnt, block_cnt, trace, lstart, llen, lower;
@@ -217,17 +177,7 @@ int cooperative_capacity(Workspace &ws, int dev, int *out) {
     return IPGC_OK;
 }
 
-// Options after validation.
-struct Params {
-    int light_max = kDefaultLightMax;
-    int hub_min = kDefaultHubMin;
-    bool check_ids = true;
-    bool stepped = false;
-    int64_t threshold = 0;  // 0: floor(6n/10) for HYBRID
-    int workgroups = 0;     // 0: automatic
-    int mode = IPGC_MODE_HYBRID;
-    ipgc_profile *prof = nullptr;
-};
+}  // namespace
 
 int parse_options(const ipgc_options *opt, int mode, Params *p) {
     if (mode != IPGC_MODE_TOPOLOGY && mode != IPGC_MODE_DATA && mode != IPGC_MODE_HYBRID)
@@ -265,6 +215,8 @@ int parse_options(const ipgc_options *opt, int mode, Params *p) {
     }
     return IPGC_OK;
 }
+
+namespace {
 
 Workspace &workspace(int dev) {
     if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
@@ -367,8 +319,8 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
 
     // Rounds: at most n (the worklist shrinks every round), plus the start of the one that finds it empty.
     if (coop > 0) {
-        int32_t max_rounds = (int32_t)std::min<int64_t>(n + 1, INT32_MAX - 2);
-        void *args[] = {&d, &max_rounds};
+        int32_t first = 1, last = (int32_t)std::min<int64_t>(n + 1, INT32_MAX - 2);
+        void *args[] = {&d, &first, &last};
         TRY(pf.begin(kKindRounds));
         HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rounds<DevT<Off>>), dim3(grid),
                                            dim3(kRoundBlock), args, 0, s));
@@ -516,7 +468,7 @@ int batch_impl(int64_t graphs, const int64_t *node_off, const int64_t *edge_off,
     d.colidx = colidx_packed;
     d.gbase = ws.gbase.p;
     d.gidx = ws.gidx.p;
-    d.node_off = ws.node_off.p;
+    d.gend = ws.node_off.p + 1;
     d.grounds = ws.grounds.p;
     d.c = out_colors_packed;
     int32_t rounds = -1;

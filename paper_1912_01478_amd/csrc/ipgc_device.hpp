@@ -123,6 +123,7 @@ struct Counters {
 // A committed hub waiting for the push step.
 struct HubRec {
     int64_t b, e;   // row entries
+    int64_t fsh;    // byte-map shift of its graph
     int32_t t;      // its color
     int32_t base;   // first global id of its graph
 };
@@ -136,11 +137,14 @@ struct DevT {
     const int32_t *colidx;   // column indices (a batch: ids local to each graph)
     const int32_t *gbase;    // a batch: first global id of each node's graph (null for one graph)
     const int32_t *gidx;     // a batch: graph index of each node (null for one graph)
-    const int64_t *node_off; // a batch: first global id of each graph, graphs + 1 entries
+    const int64_t *gend;     // a batch: one past the last global id of each graph
     int32_t *grounds;        // a batch: rounds per graph (the last round one of its nodes committed)
+    int32_t *gleft;          // a server: uncommitted nodes per graph (null otherwise)
+    const int64_t *gfshift;  // a server: byte-map shift per graph (null: no shift)
     int32_t *c;              // color state (caller's output)
     const int8_t *cls;       // class per node
-    uint8_t *F;              // byte maps: node v's map is bytes [rowptr[v] + v, rowptr[v + 1] + v]
+    uint8_t *F;              // byte maps: node v's map is bytes [rowptr[v] + v, rowptr[v + 1] + v], shifted
+                             // by fshift(v)
     int32_t *lower;          // ring of smaller neighbours per W/M node (region rowptr[v] .. + d)
     int32_t *lstart;         // ring start per node
     int32_t *llen;           // ring length per node
@@ -171,7 +175,9 @@ struct DevT {
     // global id of a neighbour stored in row entry k of node v
     __device__ __forceinline__ int32_t base(int32_t v) const { return gbase ? gbase[v] : 0; }
     // one past the last valid neighbour id of node v (its graph's end)
-    __device__ __forceinline__ int64_t id_end(int32_t v) const { return gidx ? node_off[gidx[v] + 1] : n; }
+    __device__ __forceinline__ int64_t id_end(int32_t v) const { return gidx ? gend[gidx[v]] : n; }
+    // shift of the byte maps of node v's graph (every neighbour of v shares it)
+    __device__ __forceinline__ int64_t fshift(int32_t v) const { return gfshift ? gfshift[gidx[v]] : 0; }
 };
 
 // Byte map of node w: bytes [pos, pos + size) for colors 1..size.
@@ -181,9 +187,9 @@ struct MapRef {
 };
 
 template <class D>
-__device__ __forceinline__ MapRef map_of(const D &d, int32_t w) {
+__device__ __forceinline__ MapRef map_of(const D &d, int32_t w, int64_t fsh) {
     const int64_t a = d.rowptr[w], e = d.rowptr[w + 1];
-    return MapRef{(uint64_t)a + (uint64_t)w, (uint32_t)(e - a) + 1u};
+    return MapRef{(uint64_t)(a + w + fsh), (uint32_t)(e - a) + 1u};
 }
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -437,61 +443,63 @@ __global__ __launch_bounds__(kPrepBlock) void k_check_light(D d) {
     if (__ballot(unsorted) && lane_id() == 0) d.ct->unsorted = 1;
 }
 
-// Per W/M node (a wavefront each), in one pass over its row: check the ids
-// (inside [0, n), strictly ascending) and fill its ring of smaller neighbours.
-// Within the node's region [0, d), smaller neighbours of class L are written
-// upward from position 0 and those of class W or M downward from position
-// d - 1 and then reversed, so the ring starts at the W/M part and wraps around
-// into the L part, both in ascending id order: neighbours of high degree come
-// first in every scan.
+// Ring of W/M node v, built by one wavefront in one pass over its row, which
+// it also checks (ids inside [lo, hi), strictly ascending).  Within the node's
+// region [0, d), smaller neighbours of class L are written upward from position
+// 0 and those of class W or M downward from position d - 1 and then reversed,
+// so the ring starts at the W/M part and wraps around into the L part, both in
+// ascending id order: neighbours of high degree come first in every scan.
+template <class D>
+__device__ void ring_build_wave(const D &d, int32_t v, int64_t lo, int64_t hi, int &bad, int &unsorted) {
+    const int lane = lane_id();
+    const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
+    const int32_t cap = (int32_t)(e - b);
+    int32_t nl = 0, nh = 0;  // smaller neighbours of class L / of class W or M written so far
+    for (int64_t k0 = b; k0 < e; k0 += kWave) {
+        const int64_t k = k0 + lane;
+        int q = -1;
+        int32_t u = -1;
+        if (k < e) {
+            const int64_t ug = (int64_t)d.colidx[k] + lo;
+            const bool ok = ug >= lo && ug < hi;
+            bad |= !ok;
+            if (k + 1 < e) unsorted |= ((int64_t)d.colidx[k + 1] + lo <= ug);
+            u = (int32_t)ug;
+            if (ok && u < v) q = d.cls[u] == kL ? 0 : 1;
+        }
+        const uint64_t m0 = __ballot(q == 0), m1 = __ballot(q == 1);
+        if (q == 0) d.lower[b + nl + __popcll(m0 & lanes_below())] = u;
+        if (q == 1) d.lower[b + cap - 1 - (nh + __popcll(m1 & lanes_below()))] = u;
+        nl += __popcll(m0);
+        nh += __popcll(m1);
+    }
+    // the W/M part was written downward; reverse it so both parts run in ascending id order
+    int32_t *wm = d.lower + b + cap - nh;
+    for (int32_t j = lane; j < nh / 2; j += kWave) {
+        const int32_t x = wm[j], y = wm[nh - 1 - j];
+        wm[j] = y;
+        wm[nh - 1 - j] = x;
+    }
+    if (lane == 0) {
+        d.lstart[v] = nh > 0 ? cap - nh : 0;
+        d.llen[v] = nl + nh;
+    }
+}
+
+// Rings of every W/M node (a wavefront each), with the checks of their rows.
 template <class D>
 __global__ __launch_bounds__(kPrepBlock) void k_prep_wide(D d) {
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
-    const int lane = lane_id();
     const int32_t nWide = d.ct->class_n[kW] + d.ct->class_n[kM];
     const int32_t *listWide = d.static_list + d.ct->static_off[kW];
     int bad = 0, unsorted = 0;
     for (int64_t i = gw; i < nWide; i += nw) {
         const int32_t v = listWide[i];
-        const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
-        const int32_t cap = (int32_t)(e - b);
-        const int64_t lo = d.base(v), hi = d.id_end(v);
-        int32_t nl = 0, nh = 0;  // smaller neighbours of class L / of class W or M written so far
-        for (int64_t k0 = b; k0 < e; k0 += kWave) {
-            const int64_t k = k0 + lane;
-            int q = -1;
-            int32_t u = -1;
-            if (k < e) {
-                const int64_t ug = (int64_t)d.colidx[k] + lo;
-                const bool ok = ug >= lo && ug < hi;
-                bad |= !ok;
-                if (k + 1 < e) unsorted |= ((int64_t)d.colidx[k + 1] + lo <= ug);
-                u = (int32_t)ug;
-                if (ok && u < v) q = d.cls[u] == kL ? 0 : 1;
-            }
-            const uint64_t m0 = __ballot(q == 0), m1 = __ballot(q == 1);
-            if (q == 0) d.lower[b + nl + __popcll(m0 & lanes_below())] = u;
-            if (q == 1) d.lower[b + cap - 1 - (nh + __popcll(m1 & lanes_below()))] = u;
-            nl += __popcll(m0);
-            nh += __popcll(m1);
-        }
-        // the W/M part was written downward; reverse it so both parts run in ascending id order
-        {
-            int32_t *wm = d.lower + b + cap - nh;
-            for (int32_t j = lane; j < nh / 2; j += kWave) {
-                const int32_t x = wm[j], y = wm[nh - 1 - j];
-                wm[j] = y;
-                wm[nh - 1 - j] = x;
-            }
-        }
-        if (lane == 0) {
-            d.lstart[v] = nh > 0 ? cap - nh : 0;
-            d.llen[v] = nl + nh;
-        }
+        ring_build_wave(d, v, d.base(v), d.id_end(v), bad, unsorted);
     }
-    if (__ballot(bad) && lane == 0) d.ct->bad_ids = 1;
-    if (__ballot(unsorted) && lane == 0) d.ct->unsorted = 1;
+    if (__ballot(bad) && lane_id() == 0) d.ct->bad_ids = 1;
+    if (__ballot(unsorted) && lane_id() == 0) d.ct->unsorted = 1;
 }
 
 // A packed batch seen as one graph: union row starts (local offsets of graph
@@ -499,7 +507,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep_wide(D d) {
 // and each node's graph index.  A workgroup per graph at a time; also checks
 // each graph's row pointers (local rowptr[0] == 0, rowptr[n_g] == m_g,
 // non-decreasing) and flags bad_rows.
-__global__ __launch_bounds__(kPrepBlock) void k_batch_union(const int64_t *node_off, const int64_t *edge_off,
+static __global__ __launch_bounds__(kPrepBlock) void k_batch_union(const int64_t *node_off, const int64_t *edge_off,
                                                             const int32_t *rowptr_packed, int64_t graphs,
                                                             int64_t *growptr, int32_t *gbase, int32_t *gidx,
                                                             Counters *ct) {
@@ -667,7 +675,7 @@ __device__ void assign_step(const D &d, const RoundIn &in, Units &un) {
         const int32_t v = in.cv[kL].at((int32_t)i);
         const int32_t cv = d.c[v];
         if (in.topo && cv > 0) continue;
-        d.c[v] = -first_free_word(d.F, map_of(d, v), cv < 0 ? (uint32_t)(-cv) - 1u : 0u, un);
+        d.c[v] = -first_free_word(d.F, map_of(d, v, d.fshift(v)), cv < 0 ? (uint32_t)(-cv) - 1u : 0u, un);
         un.u[kUAssignNodes] += 1;
     }
     // classes W and M: a wavefront per node, first free byte of the byte map
@@ -676,7 +684,7 @@ __device__ void assign_step(const D &d, const RoundIn &in, Units &un) {
         const int32_t v = i < nW ? in.cv[kW].at((int32_t)i) : in.cv[kM].at((int32_t)(i - nW));
         const int32_t cv = d.c[v];
         if (in.topo && cv > 0) continue;
-        const MapRef fm = map_of(d, v);
+        const MapRef fm = map_of(d, v, d.fshift(v));
         uint32_t s = cv < 0 ? (uint32_t)(-cv) - 1u : 0u;  // the previous tentative color, 0-based
         int32_t t = (int32_t)fm.size;  // d + 1 is free if nothing smaller is
         for (; s < fm.size; s += kWave) {
@@ -703,17 +711,12 @@ __device__ void assign_step(const D &d, const RoundIn &in, Units &un) {
 // the byte maps of their neighbours at once, M winners are recorded for the
 // push step; losers go to the workgroup's segment of the out list.
 
-template <class D>
-__device__ __forceinline__ void push_color(const D &d, int32_t w, int32_t t) {
-    const MapRef fm = map_of(d, w);
-    if ((uint32_t)t <= fm.size) d.F[fm.pos + t - 1] = 1;
-}
-
 // Write color t into the byte maps of the neighbours in row entries [b, e)
-// (neighbour ids offset by `base`), one wavefront, four independent loads in
-// flight per lane.
+// (neighbour ids offset by `base`, their maps by `fsh`), one wavefront, four
+// independent loads in flight per lane.
 template <class D>
-__device__ __forceinline__ void push_row_wave(const D &d, int64_t b, int64_t e, int32_t t, int32_t base) {
+__device__ __forceinline__ void push_row_wave(const D &d, int64_t b, int64_t e, int32_t t, int32_t base,
+                                              int64_t fsh) {
     const int lane = lane_id();
     for (int64_t k0 = b; k0 < e; k0 += 4 * kWave) {
         int32_t w[4];
@@ -724,7 +727,7 @@ __device__ __forceinline__ void push_row_wave(const D &d, int64_t b, int64_t e, 
         }
         MapRef fm[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? map_of(d, w[j]) : MapRef{0, 0};
+        for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? map_of(d, w[j], fsh) : MapRef{0, 0};
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if ((uint32_t)t <= fm[j].size) d.F[fm[j].pos + t - 1] = 1;
@@ -815,11 +818,12 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
                 d.c[v] = t;
                 un.u[kUCommits] += 1;
                 if (d.grounds) atomicMax(&d.grounds[d.gidx[v]], r);
+                if (d.gleft) atomicSub(&d.gleft[d.gidx[v]], 1);
             }
             if (hub) {
-                if (lane == 0) d.hub_won[atomicAdd(&d.ct->hub_winners, 1)] = HubRec{b, e, t, d.base(v)};
+                if (lane == 0) d.hub_won[atomicAdd(&d.ct->hub_winners, 1)] = HubRec{b, e, d.fshift(v), t, d.base(v)};
             } else {
-                push_row_wave(d, b, e, t, d.base(v));
+                push_row_wave(d, b, e, t, d.base(v), d.fshift(v));
                 un.u[kUPushEntries] += lane == 0 ? e - b : 0;
             }
         }
@@ -861,13 +865,14 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
         } else {
             d.c[v] = t;
             un.u[kUCommits] += 1;
+            const int64_t fsh = d.fshift(v);
             for (int64_t k0 = b; k0 < e; k0 += 4) {
                 int32_t w[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) w[j] = k0 + j < e ? d.colidx[k0 + j] + gb : -1;
                 MapRef fm[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? map_of(d, w[j]) : MapRef{0, 0};
+                for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? map_of(d, w[j], fsh) : MapRef{0, 0};
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     if ((uint32_t)t <= fm[j].size) d.F[fm[j].pos + t - 1] = 1;
@@ -882,8 +887,15 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
             if (cm) {
                 const int leader = __ffsll((unsigned long long)cm) - 1;
                 const int32_t gl = __shfl(g, leader);
-                if (lane == leader) atomicMax(&d.grounds[gl], r);
-                if (com && g != gl) atomicMax(&d.grounds[g], r);
+                const uint64_t same = __ballot(com && g == gl);
+                if (lane == leader) {
+                    atomicMax(&d.grounds[gl], r);
+                    if (d.gleft) atomicSub(&d.gleft[gl], (int32_t)__popcll(same));
+                }
+                if (com && g != gl) {
+                    atomicMax(&d.grounds[g], r);
+                    if (d.gleft) atomicSub(&d.gleft[g], 1);
+                }
             }
         }
     }
@@ -901,7 +913,7 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
 template <class D>
 __device__ void hub_push_step(const D &d, int32_t nwon, Units &un) {
     constexpr int kChunk = 4 * kWave;
-    __shared__ int64_t s_b[kRoundBlock], s_e[kRoundBlock];
+    __shared__ int64_t s_b[kRoundBlock], s_e[kRoundBlock], s_fsh[kRoundBlock];
     __shared__ int32_t s_t[kRoundBlock], s_base[kRoundBlock], s_pre[kRoundBlock + 1];
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
@@ -914,6 +926,7 @@ __device__ void hub_push_step(const D &d, int32_t nwon, Units &un) {
             s_e[threadIdx.x] = rec.e;
             s_t[threadIdx.x] = rec.t;
             s_base[threadIdx.x] = rec.base;
+            s_fsh[threadIdx.x] = rec.fsh;
             chunks = (int32_t)((rec.e - rec.b + kChunk - 1) / kChunk);
         }
         int total;
@@ -930,7 +943,7 @@ __device__ void hub_push_step(const D &d, int32_t nwon, Units &un) {
                 else hi = mid;
             }
             const int64_t k0 = s_b[lo] + (g - s_pre[lo]) * kChunk;
-            push_row_wave(d, k0, min<int64_t>(k0 + kChunk, s_e[lo]), s_t[lo], s_base[lo]);
+            push_row_wave(d, k0, min<int64_t>(k0 + kChunk, s_e[lo]), s_t[lo], s_base[lo], s_fsh[lo]);
             if (lane_id() == 0) un.u[kUPushEntries] += min<int64_t>(k0 + kChunk, s_e[lo]) - k0;
         }
         __syncthreads();
@@ -996,17 +1009,19 @@ __device__ __forceinline__ void tick(const D &d, int64_t i) {
     if (blockIdx.x == 0 && threadIdx.x == 0 && i < d.tick_cap) d.ticks[i] = wall_clock64();
 }
 
-// Every round in one cooperative launch: assign | barrier | conflict | barrier
-// [| hub push | barrier].  Every workgroup reads the same counts after each
-// barrier, so all take the same branches and leave the loop together.
+// Rounds first .. last (or until the worklist is empty) in one cooperative
+// launch: assign | barrier | conflict | barrier [| hub push | barrier].  Every
+// workgroup reads the same counts after each barrier, so all take the same
+// branches and leave the loop together.  Round 1 reads the static list; a
+// later first round reads the segmented list of its parity.
 template <class D>
-__global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t max_rounds) {
+__global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int32_t last) {
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
     GridBarrier gb;
     gb.setup(d.bar);
     Units un;
-    int32_t r = 1;
-    for (; r <= max_rounds; ++r) {
+    int32_t r = first;
+    for (; r <= last; ++r) {
         if (r > 1) load_segments(d, r & 1, pre);
         const RoundIn in = round_view(d, r, pre);
         if (blockIdx.x == 0) round_record(d, r, in, false);

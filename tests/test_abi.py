@@ -82,3 +82,10 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(pkg, "_lib", None)
     with pytest.raises(ImportError):
         pkg.library()
+
+
+def test_server_struct_layouts():
+    import paper_1912_01478_amd as pkg
+    assert ctypes.sizeof(pkg.ServerConfig) == 8 + 8 + 4 * 4 + 40
+    assert ctypes.sizeof(pkg.JobResult) == 16
+    assert ctypes.sizeof(pkg.ServerStats) == 11 * 8 + 16 * 8

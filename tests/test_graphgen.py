@@ -81,3 +81,14 @@ def test_batch_recipe_parameters():
     assert all(p["kind"] == ("er" if i % 2 == 0 else "rmat") for i, p in enumerate(ps))
     assert {p["avg_degree"] for p in ps[0::2]} == set(range(4, 33))
     assert {p["edge_factor"] for p in ps[1::2]} == set(range(8, 17))
+
+
+def test_serving_jobs_mix_and_identity():
+    ps = [gg.serving_job_params(5, i) for i in range(2000)]
+    big = sum(p["n"] == 1 << 20 and p["kind"] == "rmat" for p in ps)
+    assert 150 <= big <= 250  # about 10% R-MAT scale-20 jobs
+    small = [i for i, p in enumerate(ps) if p["n"] < 5000][:6]
+    pb = gg.pack_params([ps[i] for i in small])
+    for j, i in enumerate(small):
+        a, b = pb.graph(j), gg.params_graph(ps[i])
+        assert (a.rowptr == b.rowptr).all() and (a.colidx == b.colidx).all()
