@@ -72,6 +72,7 @@ constexpr int kRoundWaves = kRoundBlock / kWave;
 constexpr int kMaxRoundBlocks = 1024;    // cap on the cooperative grid
 constexpr int kLightMaxLimit = 32;       // thread-per-node pull uses a 64-bit mask: d + 1 <= 64
 constexpr int kMaxXcc = 16;
+constexpr int kWideScanMax = 65536;      // rounds with at most this many active nodes scan rings 4 chunks a pass
 
 enum { kL = 0, kW = 1, kM = 2, kNumClasses = 3 };
 
@@ -736,42 +737,60 @@ __device__ __forceinline__ void push_row_wave(const D &d, int64_t b, int64_t e, 
 
 // Ring scan of W/M node v by one wavefront: looks for a smaller neighbour with
 // tentative color t, drops committed neighbours, keeps the others (moved to the
-// ring's end) and advances the ring start past every entry it read.  Reads at
-// least one chunk; stops after the chunk in which a conflict shows up.
+// ring's end) and advances the ring start past every entry it read.  The first
+// pass reads one chunk of 64 entries, later passes `wide` (1..4) chunks, with as
+// many independent loads in flight per lane; stops after the pass in which a
+// conflict shows up.  Wide passes pay off in small, latency-bound rounds; in
+// large rounds the extra entries a loser reads cost more bandwidth than they
+// save in latency.  Kept entries are written past the ring's end, which never
+// reaches an entry not yet read: at most `read` entries are kept and the ring
+// never holds more than d entries.
 template <class D>
-__device__ bool ring_scan_wave(const D &d, int32_t v, int32_t t, Units &un) {
+__device__ bool ring_scan_wave(const D &d, int32_t v, int32_t t, int wide, Units &un) {
+    constexpr int kPass = 4;
     const int lane = lane_id();
     const int64_t base = d.rowptr[v];
     const int32_t cap = (int32_t)(d.rowptr[v + 1] - base);
     int32_t start = d.lstart[v], len = d.llen[v];
     int32_t read = 0, kept = 0;
     bool lose = false;
+    int chunks = 1;  // the first pass reads one chunk (a loser often stops there), later passes `wide`
     while (read < len && !lose) {
-        const int32_t k = read + lane;
-        int32_t u = -1, cu = 0;
-        if (k < len) {
-            int32_t p = start + k;
-            if (p >= cap) p -= cap;
-            u = d.lower[base + p];
-            cu = d.c[u];
+        int32_t u[kPass], cu[kPass];
+#pragma unroll
+        for (int j = 0; j < kPass; ++j) {
+            const int32_t k = read + j * kWave + lane;
+            u[j] = -1;
+            if (j < chunks && k < len) {
+                int32_t p = start + k;
+                if (p >= cap) p -= cap;
+                u[j] = d.lower[base + p];
+            }
         }
-        const bool hit = u >= 0 && iabs(cu) == t;
-        const bool keep = u >= 0 && cu < 0;
+#pragma unroll
+        for (int j = 0; j < kPass; ++j) cu[j] = u[j] >= 0 ? d.c[u[j]] : 0;
+        bool hit = false;
+#pragma unroll
+        for (int j = 0; j < kPass; ++j) {
+            hit |= u[j] >= 0 && iabs(cu[j]) == t;
+            const bool keep = u[j] >= 0 && cu[j] < 0;
+            const uint64_t km = __ballot(keep);
+            if (keep) {
+                int32_t p = start + len + kept + __popcll(km & lanes_below());
+                while (p >= cap) p -= cap;
+                d.lower[base + p] = u[j];
+            }
+            kept += __popcll(km);
+        }
         lose = __ballot(hit) != 0;
-        const uint64_t km = __ballot(keep);
-        if (keep) {
-            int32_t p = start + len + kept + __popcll(km & lanes_below());
-            while (p >= cap) p -= cap;
-            d.lower[base + p] = u;
-        }
-        kept += __popcll(km);
-        read += min(kWave, len - read);
+        read += min(chunks * kWave, len - read);
+        chunks = wide;
     }
     un.u[kUConflictEntries] += lane == 0 ? read : 0;
     un.u[kUListWrites] += lane == 0 ? kept : 0;
     if (lane == 0 && len > 0) {
         int32_t s2 = start + read;
-        if (s2 >= cap) s2 -= cap;
+        while (s2 >= cap) s2 -= cap;
         d.lstart[v] = s2;
         d.llen[v] = len - read + kept;
     }
@@ -803,7 +822,7 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
         const int32_t cv = d.c[v];
         if (in.topo && cv > 0) continue;
         const int32_t t = -cv;
-        const bool lose = ring_scan_wave(d, v, t, un);
+        const bool lose = ring_scan_wave(d, v, t, in.total <= kWideScanMax ? 4 : 1, un);
         const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
         const int q = hub ? kM : kW;
         if (lane == 0) un.u[kUConflictNodes] += 1;
