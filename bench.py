@@ -97,6 +97,8 @@ def parse():
     p.add_argument("--batch-graphs", type=int, default=4096, help="--config 4: number of graphs")
     p.add_argument("--mode", default=None, choices=["hybrid", "data", "topology"],
                    help="round schedule (default: the tuned one for the workload's class, else hybrid)")
+    p.add_argument("--light", default=None, choices=["auto", "pull", "push"],
+                   help="how light nodes learn their neighbours' colors (default: tuned, else auto)")
     p.add_argument("--tune-table", default=None, help="JSON table of tuned options (default: the package's)")
     p.add_argument("--autotune", action="store_true", help="tune the options on this workload first and store them")
     p.add_argument("--no-tuning", action="store_true", help="use the library's default options")
@@ -376,6 +378,8 @@ def main():
     tuned = dict(at.DEFAULT if choice is None else choice)
     if args.mode:
         tuned["schedule"] = args.mode
+    if args.light:
+        tuned["light"] = args.light
     kw = at.call_kwargs(tuned, w.n)
     mode = kw["mode"]
     log("options (%s, class %s): %s" % ("tuned" if choice else "defaults", at.class_key(feats), kw))

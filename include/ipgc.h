@@ -116,8 +116,12 @@ typedef struct ipgc_options {
 
 /* Option flags. */
 enum {
-    IPGC_FLAG_STEPPED = 1      /* one launch per round step instead of one cooperative launch for all
+    IPGC_FLAG_STEPPED = 1,     /* one launch per round step instead of one cooperative launch for all
                                   rounds (same result; used for per-step timing) */
+    IPGC_FLAG_LIGHT_PULL = 2,  /* nodes of degree <= light_max_degree read their neighbours' colors in
+                                  every assign instead of receiving them in a byte map (same result) */
+    IPGC_FLAG_LIGHT_PUSH = 4   /* every committed color is written into every neighbour's byte map.
+                                  Neither flag: pull when no node is above light_max_degree, else push */
 };
 
 /* Per-round record, filled on request.  Host memory owned by the caller. */

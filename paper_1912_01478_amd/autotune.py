@@ -2,9 +2,10 @@
 
 The options of a coloring call -- the round kernels' workgroup count, the degree cut-offs of the
 node classes (thread per node up to ``light_max_degree``, wavefront per node up to
-``hub_min_degree``, hubs above), and the round schedule with its threshold H (Section IV leaves H
-as a tuning parameter; an analytical H is named there as future work) -- change only the time of
-a call, never its colors or round count.  The tuner searches them per graph class by coordinate
+``hub_min_degree``, hubs above), whether light nodes pull their neighbours' colors or receive them
+in byte maps, and the round schedule with its threshold H (Section IV leaves H as a tuning
+parameter; an analytical H is named there as future work) -- change only the time of a call,
+never its colors or round count.  The tuner searches them per graph class by coordinate
 descent over measured device times and keeps the winners in a JSON table keyed by class.
 
 A graph class is a bucket of cheap structural features: node count, average degree and degree
@@ -23,8 +24,9 @@ KNOBS = {
     "light_max_degree": [0, 8, 16],
     "hub_min_degree": [0, 256, 4096, 16384],
     "schedule": ["hybrid", "data", "hybrid_h2", "hybrid_h10", "topology"],
+    "light": ["auto", "pull", "push"],
 }
-DEFAULT = {"workgroups": 0, "light_max_degree": 0, "hub_min_degree": 0, "schedule": "hybrid"}
+DEFAULT = {"workgroups": 0, "light_max_degree": 0, "hub_min_degree": 0, "schedule": "hybrid", "light": "auto"}
 TABLE_VERSION = 1
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_options.json")
 
@@ -45,6 +47,7 @@ def call_kwargs(choice: dict, n: int) -> dict:
     kw = schedule_args(choice.get("schedule", "hybrid"), n)
     for k in ("workgroups", "light_max_degree", "hub_min_degree"):
         kw[k] = int(choice.get(k, 0))
+    kw["light"] = choice.get("light", "auto")
     lm = kw["light_max_degree"] or 32
     if kw["hub_min_degree"] and kw["hub_min_degree"] <= lm:
         kw["hub_min_degree"] = lm + 1

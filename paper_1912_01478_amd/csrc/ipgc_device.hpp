@@ -76,6 +76,14 @@ constexpr int kWideScanMax = 65536;      // rounds with at most this many active
 
 enum { kL = 0, kW = 1, kM = 2, kNumClasses = 3 };
 
+// How committed colors reach the nodes of class L:
+//   kPushAll   every winner writes its color into every neighbour's byte map;
+//   kPullLight L nodes read their neighbours' colors in each assign (a register
+//              mask: d + 1 <= 33 colors matter), winners write only into the maps
+//              of W/M neighbours;
+//   kPullOnly  as kPullLight on a graph with no W/M node: nobody writes maps.
+enum { kPushAll = 0, kPullLight = 1, kPullOnly = 2 };
+
 // Work counters (units for the algorithmic byte count).
 enum {
     kUAssignNodes = 0,  // nodes given a tentative color
@@ -171,7 +179,7 @@ struct DevT {
     int32_t hub_min;         // degree above which a node is class M
     int32_t sorted;          // every row strictly ascending
     int32_t grid;            // workgroups of the round kernels (segments per class)
-    int32_t pad;
+    int32_t light_pull;      // kPushAll, kPullLight or kPullOnly: how class L learns its neighbours' colors
 
     // global id of a neighbour stored in row entry k of node v
     __device__ __forceinline__ int32_t base(int32_t v) const { return gbase ? gbase[v] : 0; }
@@ -317,7 +325,9 @@ __global__ __launch_bounds__(kPrepBlock) void k_init(D d, int8_t *cls, int32_t s
     int64_t deg[kNumClasses] = {0, 0, 0};
     int bad = 0;
     for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
-        d.c[v] = 0;
+        // Round 1 assigns color 1 to every node (no neighbour is committed yet), so the state
+        // starts there: tentative color 1, and round 1 skips its assign step.
+        d.c[v] = -1;
         const int64_t a = d.rowptr[v], e = d.rowptr[v + 1];
         const bool b = a < 0 || e < a || e > d.m || e - a >= INT32_MAX;
         bad |= b;
@@ -671,12 +681,29 @@ __device__ void assign_step(const D &d, const RoundIn &in, Units &un) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
     const int64_t gw = gt / kWave, nw = nt / kWave;
     const int lane = lane_id();
-    // class L: a thread per node, first free byte of the byte map, read a 4-byte word at a time
+    // class L: a thread per node; first free byte of the byte map (a 4-byte word at a time), or
+    // first zero bit of a mask of the neighbours' committed colors (four loads in flight)
     for (int64_t i = gt; i < in.cv[kL].total; i += nt) {
         const int32_t v = in.cv[kL].at((int32_t)i);
         const int32_t cv = d.c[v];
         if (in.topo && cv > 0) continue;
-        d.c[v] = -first_free_word(d.F, map_of(d, v, d.fshift(v)), cv < 0 ? (uint32_t)(-cv) - 1u : 0u, un);
+        if (d.light_pull == kPushAll) {
+            d.c[v] = -first_free_word(d.F, map_of(d, v, d.fshift(v)), cv < 0 ? (uint32_t)(-cv) - 1u : 0u, un);
+        } else {
+            const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
+            const int32_t gb = d.base(v);
+            uint64_t used = 0;
+            for (int64_t k0 = b; k0 < e; k0 += 4) {
+                int32_t cu[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) cu[j] = k0 + j < e ? d.c[d.colidx[k0 + j] + gb] : 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (cu[j] > 0 && cu[j] <= 64) used |= 1ull << (cu[j] - 1);
+            }
+            d.c[v] = -__ffsll((unsigned long long)~used);
+            un.u[kUPullEntries] += e - b;
+        }
         un.u[kUAssignNodes] += 1;
     }
     // classes W and M: a wavefront per node, first free byte of the byte map
@@ -725,6 +752,11 @@ __device__ __forceinline__ void push_row_wave(const D &d, int64_t b, int64_t e, 
         for (int j = 0; j < 4; ++j) {
             const int64_t k = k0 + j * kWave + lane;
             w[j] = k < e ? d.colidx[k] + base : -1;
+        }
+        if (d.light_pull == kPullLight) {  // L neighbours read colors themselves
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (w[j] >= 0 && d.cls[w[j]] == kL) w[j] = -1;
         }
         MapRef fm[4];
 #pragma unroll
@@ -885,10 +917,15 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
             d.c[v] = t;
             un.u[kUCommits] += 1;
             const int64_t fsh = d.fshift(v);
-            for (int64_t k0 = b; k0 < e; k0 += 4) {
+            for (int64_t k0 = b; k0 < e && d.light_pull != kPullOnly; k0 += 4) {
                 int32_t w[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) w[j] = k0 + j < e ? d.colidx[k0 + j] + gb : -1;
+                if (d.light_pull == kPullLight) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (w[j] >= 0 && d.cls[w[j]] == kL) w[j] = -1;
+                }
                 MapRef fm[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? map_of(d, w[j], fsh) : MapRef{0, 0};
@@ -896,7 +933,7 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
                 for (int j = 0; j < 4; ++j)
                     if ((uint32_t)t <= fm[j].size) d.F[fm[j].pos + t - 1] = 1;
             }
-            un.u[kUPushEntries] += e - b;
+            un.u[kUPushEntries] += d.light_pull == kPullOnly ? 0 : e - b;
         }
         if (d.grounds) {
             // lanes committing nodes of the same graph as the first committing lane share one atomic
@@ -1046,8 +1083,10 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
         if (blockIdx.x == 0) round_record(d, r, in, false);
         if (in.total == 0) break;
         tick(d, 3 * (int64_t)(r - 1));
-        assign_step(d, in, un);
-        gb.sync();
+        if (r > 1) {  // round 1's tentative colors (all 1) were set at init
+            assign_step(d, in, un);
+            gb.sync();
+        }
         tick(d, 3 * (int64_t)(r - 1) + 1);
         conflict_step(d, in, out_segs(d, r), r, un);
         gb.sync();
@@ -1073,7 +1112,7 @@ __global__ __launch_bounds__(kRoundBlock) void k_assign_round(D d, int32_t r) {
     if (r > 1) load_segments(d, r & 1, pre);
     const RoundIn in = round_view(d, r, pre);
     if (blockIdx.x == 0) round_record(d, r, in, true);
-    if (in.total == 0) return;
+    if (in.total == 0 || r == 1) return;  // round 1's tentative colors were set at init
     Units un;
     assign_step(d, in, un);
     un.flush(d);

@@ -71,6 +71,7 @@ struct Params {
     bool stepped = false;
     int64_t threshold = 0;  // 0: floor(6n/10) for HYBRID
     int workgroups = 0;     // 0: automatic
+    int light = -1;         // -1: automatic, 0: push into every byte map, 1: class L pulls
     int mode = IPGC_MODE_HYBRID;
     ipgc_profile *prof = nullptr;
 };

@@ -331,7 +331,7 @@ int Server::create(const ipgc_server_config &cfg) {
     if (cfg.node_capacity >= INT32_MAX) return fail(IPGC_ETOOBIG, "node_capacity must be below 2^31 - 1");
     TRY(parse_options(&cfg.options, cfg.mode, &P));
     if (!P.check_ids) return fail(IPGC_EINVAL, "a server checks every job: validate must not be NONE");
-    if (P.stepped || P.prof) return fail(IPGC_EINVAL, "server options take no flags and no profile");
+    if (P.stepped || P.prof) return fail(IPGC_EINVAL, "a server takes no profile and no IPGC_FLAG_STEPPED");
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     quantum = cfg.rounds_per_step > 0 ? cfg.rounds_per_step : kDefaultQuantum;
@@ -453,6 +453,7 @@ SDev Server::dev_view(int64_t nhigh, int64_t threshold) {
     d.hub_min = P.hub_min;
     d.sorted = 0;
     d.grid = grid;
+    d.light_pull = P.light == 1 ? kPullLight : kPushAll;  // jobs of any class may arrive later
     return d;
 }
 

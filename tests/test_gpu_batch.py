@@ -119,6 +119,11 @@ def test_batch_options_never_change_the_result(H, light, hub):
     assert_batch_matches_oracle(MEDIUM, "hybrid", threshold=H, light_max_degree=light, hub_min_degree=hub)
 
 
+@pytest.mark.parametrize("light", ["pull", "push"])
+def test_batch_light_modes(light):
+    assert_batch_matches_oracle(MIXED + MEDIUM[:2], "hybrid", light=light)
+
+
 def test_batch_unsorted_rows():
     graphs = MEDIUM[:3]
     csr = [gg.shuffle_rows(g, 5 + i) for i, g in enumerate(graphs)]

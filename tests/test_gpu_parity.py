@@ -124,6 +124,15 @@ def test_stepped_launches_same_result(g, mode):
     assert_parity(g, mode, stepped=True, light_max_degree=4, hub_min_degree=300)
 
 
+@pytest.mark.parametrize("light", ["pull", "push"])
+@pytest.mark.parametrize("g", SMALL, ids=lambda g: g.name)
+def test_light_pull_and_push_same_result(g, light):
+    """Light nodes reading their neighbours' colors or receiving them in byte maps: same bits,
+    in one launch and stepped, and with every node light (light_max_degree 32 covers road graphs)."""
+    assert_parity(g, "hybrid", light=light)
+    assert_parity(g, "data", light=light, stepped=True, light_max_degree=4, hub_min_degree=300)
+
+
 @pytest.mark.parametrize("g", SMALL[:4], ids=lambda g: g.name)
 def test_unsorted_rows(g):
     """Row order is irrelevant; unsorted rows also switch off the sorted-row early exit."""

@@ -75,6 +75,12 @@ def test_all_at_once_matches_oracle(mode):
         assert st["completed"] == len(MIX) and st["resident"] == 0 and st["peak_resident"] > 1
 
 
+def test_light_pull_server():
+    with _server(light="pull", rounds_per_step=5) as srv:
+        ids = {srv.submit(g.rowptr, g.colidx): g for g in MIX}
+        check(drain(srv), ids)
+
+
 def test_arrivals_while_running():
     """Jobs submitted between steps join the running mix; results are those of each job alone."""
     with _server(rounds_per_step=2) as srv:
