@@ -123,6 +123,14 @@ __global__ __launch_bounds__(256) void k_srv_prep(SDev d, int32_t v0, int64_t n,
     if (__ballot(bad) && lane == 0) gerr[slot] = 1;
 }
 
+// A job whose checks failed leaves the union before any round sees it.
+__global__ __launch_bounds__(256) void k_srv_reject(int8_t *cls, int32_t v0, int64_t cnt, int32_t slot,
+                                                    const int32_t *gerr) {
+    if (!gerr[slot]) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+        cls[v0 + i] = kNoNode;
+}
+
 // Marks node slots [v0, v0 + cnt) as belonging to no job.
 __global__ __launch_bounds__(256) void k_srv_retire(int8_t *cls, int32_t v0, int64_t cnt) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
@@ -272,11 +280,15 @@ struct Job {
     int32_t slot = -1;
     int64_t v0 = 0, e0 = 0, f0 = 0;
     int32_t r_adm = 0;
+    int64_t stage = 0;      // its row pointers' offset in the staging buffer
+    bool admitted = false;  // its admission kernels have been issued
 };
 
 struct Server {
     int dev = 0;
-    hipStream_t s = nullptr;
+    hipStream_t s = nullptr;   // every kernel
+    hipStream_t cs = nullptr;  // uploads of the next jobs, overlapping the rounds on s
+    hipEvent_t ev_uploaded = nullptr, ev_stage_free = nullptr;
     Params P;
     int quantum = kDefaultQuantum;
     int grid = 1;
@@ -297,7 +309,9 @@ struct Server {
     std::vector<int32_t> free_slots;
     std::vector<Job> slot_job;
     std::vector<int32_t> h_gleft, h_grounds, h_gerr;
-    std::deque<Job> queue;
+    std::deque<Job> queue;         // submitted, no room yet
+    std::vector<int32_t> staged;   // slots reserved and uploaded (or uploading), not yet admitted
+    int64_t stage_used = 0;
     std::vector<ipgc_job_result> done;
     int64_t next_id = 0;
     int32_t next_round = 2;  // round numbers start at 2 so that every round reads a segmented list
@@ -307,7 +321,8 @@ struct Server {
     int create(const ipgc_server_config &cfg);
     void destroy();
     SDev dev_view(int64_t nhigh, int64_t threshold);
-    int admit();
+    int reserve_and_upload();
+    int admit_staged();
     int retire(const std::vector<int32_t> &slots, int status);
     int step();
 };
@@ -334,6 +349,9 @@ int Server::create(const ipgc_server_config &cfg) {
     if (P.stepped || P.prof) return fail(IPGC_EINVAL, "a server takes no profile and no IPGC_FLAG_STEPPED");
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&ev_uploaded, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ev_stage_free, hipEventDisableTiming));
     quantum = cfg.rounds_per_step > 0 ? cfg.rounds_per_step : kDefaultQuantum;
     TRY(cooperative_grid(dev, P.workgroups, &grid));
     ncap = cfg.node_capacity;
@@ -382,6 +400,7 @@ int Server::create(const ipgc_server_config &cfg) {
     for (int k = 0; k < kNumClasses; ++k) h.seg_cap[k] = seg_cap;
     *host_ct = h;
     HIP_TRY(hipMemcpyAsync(ct, host_ct, sizeof(Counters), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ev_stage_free, s));
     HIP_TRY(hipStreamSynchronize(s));
 
     nodes.init(ncap);
@@ -408,8 +427,12 @@ void Server::destroy() {
     if (ct) (void)hipFree(ct);
     if (host_ct) (void)hipHostFree(host_ct);
     if (s) (void)hipStreamDestroy(s);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (ev_uploaded) (void)hipEventDestroy(ev_uploaded);
+    if (ev_stage_free) (void)hipEventDestroy(ev_stage_free);
     ct = host_ct = nullptr;
-    s = nullptr;
+    s = cs = nullptr;
+    ev_uploaded = ev_stage_free = nullptr;
 }
 
 SDev Server::dev_view(int64_t nhigh, int64_t threshold) {
@@ -486,10 +509,14 @@ int Server::retire(const std::vector<int32_t> &slots, int status) {
     return IPGC_OK;
 }
 
-// Admits queued jobs in FIFO order while they fit; returns after their checks.
-int Server::admit() {
-    std::vector<int32_t> admitted;
-    int64_t stage_used = 0;
+// Reserves arena ranges and a slot for queued jobs in FIFO order while they fit,
+// and uploads their CSR on the copy stream (the caller's arrays are pageable,
+// so each copy returns once its data is on its way; the rounds of the running
+// step continue meanwhile).  Their admission kernels run at the next step.
+int Server::reserve_and_upload() {
+    if (queue.empty() || free_slots.empty()) return IPGC_OK;
+    // the admission kernels of the previous step read the staging buffer
+    HIP_TRY(hipStreamWaitEvent(cs, ev_stage_free, 0));
     while (!queue.empty() && !free_slots.empty()) {
         Job j = queue.front();
         if (stage_used + j.n + 1 > ncap + 1) break;
@@ -513,44 +540,62 @@ int Server::admit() {
         j.v0 = v0;
         j.e0 = e0;
         j.f0 = f0;
-        j.r_adm = next_round - 1;
-        slot_job[slot] = j;
-        int32_t *rp_dev = stage.p + stage_used;
+        j.stage = stage_used;
         stage_used += j.n + 1;
-        // CSR in, error flag and byte maps cleared, then rows, classes and rings
-        HIP_TRY(hipMemcpyAsync(rp_dev, j.rp, sizeof(int32_t) * (j.n + 1), hipMemcpyHostToDevice, s));
-        if (j.m > 0) HIP_TRY(hipMemcpyAsync(colidx.p + e0, j.ci, sizeof(int32_t) * j.m, hipMemcpyHostToDevice, s));
-        HIP_TRY(hipMemsetAsync(gerr.p + slot, 0, sizeof(int32_t), s));
-        HIP_TRY(hipMemsetAsync(F.p + kFPad + f0, 0, j.m + j.n + 8, s));
-        const AdmitJob aj{rp_dev, j.n, j.m, e0, f0 - (e0 + v0), (int32_t)v0, slot, j.r_adm};
+        slot_job[slot] = j;
+        HIP_TRY(hipMemcpyAsync(stage.p + j.stage, j.rp, sizeof(int32_t) * (j.n + 1), hipMemcpyHostToDevice, cs));
+        if (j.m > 0) HIP_TRY(hipMemcpyAsync(colidx.p + e0, j.ci, sizeof(int32_t) * j.m, hipMemcpyHostToDevice, cs));
+        HIP_TRY(hipMemsetAsync(gerr.p + slot, 0, sizeof(int32_t), cs));
+        HIP_TRY(hipMemsetAsync(F.p + kFPad + f0, 0, j.m + j.n + 8, cs));
+        staged.push_back(slot);
+        st.admitted += 1;
+        st.resident += 1;
+        st.resident_nodes += j.n;
+        st.resident_edges += j.m;
+        st.peak_resident = std::max(st.peak_resident, st.resident);
+    }
+    HIP_TRY(hipEventRecord(ev_uploaded, cs));
+    st.queued = (int64_t)queue.size();
+    return IPGC_OK;
+}
+
+// Admission kernels of the staged jobs (after their uploads): rows, classes, state,
+// id checks and rings; a job that fails its checks leaves the union at once and is
+// reported after the step.
+int Server::admit_staged() {
+    if (staged.empty()) return IPGC_OK;
+    HIP_TRY(hipStreamWaitEvent(s, ev_uploaded, 0));
+    for (int32_t slot : staged) {
+        Job &j = slot_job[slot];
+        j.r_adm = next_round - 1;
+        const int64_t v0 = j.v0, e0 = j.e0, f0 = j.f0;
+        const AdmitJob aj{stage.p + j.stage, j.n, j.m, e0, f0 - (e0 + v0), (int32_t)v0, slot, j.r_adm};
         const int blocks = (int)std::min<int64_t>(4096, (j.n + 1 + 255) / 256);
         k_srv_admit<<<blocks, 256, 0, s>>>(aj, P.light_max, P.hub_min, growptr.p, gbase.p, gidx.p, cls.p, c.p,
                                            lstart.p, llen.p, gend.p, gfshift.p, gleft.p, grounds.p, gerr.p);
         SDev d = dev_view(nodes.high(), 0);
         const int pblocks = (int)std::min<int64_t>(8192, (j.n + 3) / 4);
         k_srv_prep<<<std::max(1, pblocks), 256, 0, s>>>(d, (int32_t)v0, j.n, slot, gerr.p);
+        k_srv_reject<<<blocks, 256, 0, s>>>(cls.p, (int32_t)v0, j.n + 1, slot, gerr.p);
         HIP_TRY(hipGetLastError());
-        admitted.push_back(slot);
-        st.admitted += 1;
-        st.resident += 1;
-        st.resident_nodes += j.n;
-        st.resident_edges += j.m;
-        st.peak_resident = std::max(st.peak_resident, st.resident);
-        static_dirty = true;
+        j.admitted = true;
     }
-    st.queued = (int64_t)queue.size();
-    if (admitted.empty()) return IPGC_OK;
-    HIP_TRY(hipMemcpyAsync(h_gerr.data(), gerr.p, sizeof(int32_t) * max_jobs, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    std::vector<int32_t> bad;
-    for (int32_t slot : admitted)
-        if (h_gerr[slot]) bad.push_back(slot);
-    return retire(bad, IPGC_EBADCSR);
+    HIP_TRY(hipEventRecord(ev_stage_free, s));
+    staged.clear();
+    stage_used = 0;
+    static_dirty = true;
+    return IPGC_OK;
 }
 
 int Server::step() {
-    TRY(admit());
-    if (st.resident == 0) return IPGC_OK;
+    if (st.resident == 0 && queue.empty()) return IPGC_OK;
+    int64_t active_jobs = 0;
+    for (const Job &j : slot_job) active_jobs += j.slot >= 0 && j.admitted;
+    // with no rounds to overlap them with, uploads happen now; otherwise during the rounds
+    if (active_jobs == 0 && staged.empty()) TRY(reserve_and_upload());
+    active_jobs += (int64_t)staged.size();
+    TRY(admit_staged());
+    if (active_jobs == 0) return IPGC_OK;
     const int64_t nhigh = nodes.high();
     int64_t H;
     if (P.mode == IPGC_MODE_TOPOLOGY) H = -1;
@@ -575,14 +620,22 @@ int Server::step() {
     HIP_TRY(hipMemcpyAsync(host_ct, ct, sizeof(Counters), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h_gleft.data(), gleft.p, sizeof(int32_t) * max_jobs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h_grounds.data(), grounds.p, sizeof(int32_t) * max_jobs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h_gerr.data(), gerr.p, sizeof(int32_t) * max_jobs, hipMemcpyDeviceToHost, s));
+    // while the rounds run: upload the next jobs that fit now
+    TRY(reserve_and_upload());
     HIP_TRY(hipStreamSynchronize(s));
     const int32_t ran_to = host_ct->finished ? host_ct->rounds : last;
     st.rounds += ran_to - first + 1;
     st.steps += 1;
     next_round = ran_to + 1;
-    std::vector<int32_t> finished;
-    for (int32_t slot = 0; slot < max_jobs; ++slot)
-        if (slot_job[slot].slot >= 0 && h_gleft[slot] == 0) finished.push_back(slot);
+    std::vector<int32_t> finished, failed;
+    for (int32_t slot = 0; slot < max_jobs; ++slot) {
+        const Job &j = slot_job[slot];
+        if (j.slot < 0 || !j.admitted) continue;
+        if (h_gerr[slot]) failed.push_back(slot);
+        else if (h_gleft[slot] == 0) finished.push_back(slot);
+    }
+    TRY(retire(failed, IPGC_EBADCSR));
     return retire(finished, IPGC_OK);
 }
 
@@ -692,6 +745,7 @@ void ipgc_server_destroy(ipgc_server *server) {
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(server->impl.dev);
     (void)hipStreamSynchronize(server->impl.s);
+    (void)hipStreamSynchronize(server->impl.cs);
     server->impl.destroy();
     (void)hipSetDevice(cur);
     delete server;
