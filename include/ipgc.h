@@ -120,8 +120,14 @@ enum {
                                   rounds (same result; used for per-step timing) */
     IPGC_FLAG_LIGHT_PULL = 2,  /* nodes of degree <= light_max_degree read their neighbours' colors in
                                   every assign instead of receiving them in a byte map (same result) */
-    IPGC_FLAG_LIGHT_PUSH = 4   /* every committed color is written into every neighbour's byte map.
+    IPGC_FLAG_LIGHT_PUSH = 4,  /* every committed color is written into every neighbour's byte map.
                                   Neither flag: pull when no node is above light_max_degree, else push */
+    IPGC_FLAG_RACY = 8         /* in-place mode: a node that loses a conflict uncolors at once (a later
+                                  test in the same step no longer sees it) and light nodes also avoid
+                                  their neighbours' visible tentative colors.  Fewer rounds, but the
+                                  colors and round count depend on timing: the result is a proper
+                                  coloring with colors in [1, deg+1], not the synchronous one.
+                                  Implies IPGC_FLAG_LIGHT_PULL unless IPGC_FLAG_LIGHT_PUSH is given. */
 };
 
 /* Per-round record, filled on request.  Host memory owned by the caller. */

@@ -37,6 +37,7 @@ EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_color_graphs_batched
 FLAG_STEPPED = 1
 FLAG_LIGHT_PULL = 2
 FLAG_LIGHT_PUSH = 4
+FLAG_RACY = 8
 LIGHT = {"auto": 0, "pull": FLAG_LIGHT_PULL, "push": FLAG_LIGHT_PUSH}
 PROFILE_KINDS = 16
 
@@ -180,7 +181,7 @@ class _Call:
     """Marshalled options, optional profile and optional trace of one library call."""
 
     def __init__(self, threshold, light_max_degree, hub_min_degree, validate, stepped, trace, trace_cap,
-                 profile_mask, timeline, workgroups=0, light="auto"):
+                 profile_mask, timeline, workgroups=0, light="auto", racy=False):
         self.prof = None
         if profile_mask or timeline:
             self.prof = Profile(int(profile_mask))
@@ -189,7 +190,7 @@ class _Call:
                 self.prof.phase_ticks = ctypes.cast(self._ticks, ctypes.POINTER(ctypes.c_uint64))
                 self.prof.phase_capacity = int(timeline)
         self.opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), int(validate),
-                            (FLAG_STEPPED if stepped else 0) | LIGHT[light],
+                            (FLAG_STEPPED if stepped else 0) | LIGHT[light] | (FLAG_RACY if racy else 0),
                             ctypes.pointer(self.prof) if self.prof is not None else None, int(workgroups), 0)
         self.tr = None
         if trace:
@@ -218,7 +219,7 @@ class _Call:
 def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_degree: int = 0,
                 hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT, stepped: bool = False, out=None,
                 stream=None, trace: bool = False, profile_mask: int = 0, timeline: int = 0,
-                workgroups: int = 0, light: str = "auto") -> Coloring:
+                workgroups: int = 0, light: str = "auto", racy: bool = False) -> Coloring:
     """Color the symmetric CSR graph (``rowptr``: int32[n+1], ``colidx``: int32[m], both on the
     HIP device) and return the 1-based colors and round count.  ``mode`` is "topology", "data"
     or "hybrid"; ``threshold`` is H for hybrid rounds (0: floor(6n/10)).  ``stepped`` runs one
@@ -227,7 +228,8 @@ def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_
     ``profile_mask`` times the selected kernel kinds with HIP events (bit k = kind k); ``timeline``
     > 0 records that many device wall-clock ticks at the round-step boundaries; ``workgroups`` sets
     the round kernels' workgroup count (0: automatic); ``light`` is "pull", "push" or "auto" (how
-    nodes of degree <= light_max_degree learn their neighbours' colors)."""
+    nodes of degree <= light_max_degree learn their neighbours' colors); ``racy`` selects the
+    in-place mode (a proper coloring that depends on timing, not the synchronous one)."""
     import torch
 
     if rowptr.dtype != torch.int32 or colidx.dtype != torch.int32:
@@ -245,7 +247,7 @@ def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_
     elif out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() or out.device != rowptr.device:
         raise ValueError("out must be a contiguous int32 tensor of n entries on the graph's device")
     call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, n, profile_mask, timeline,
-                 workgroups, light)
+                 workgroups, light, racy)
     rounds = ctypes.c_int32(-1)
     if stream is None:
         stream = torch.cuda.current_stream(rowptr.device)
@@ -301,7 +303,8 @@ class BatchColoring:
 def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode="hybrid", *, threshold: int = 0,
                          light_max_degree: int = 0, hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT,
                          stepped: bool = False, out=None, stream=None, trace: bool = False,
-                         profile_mask: int = 0, workgroups: int = 0, light: str = "auto") -> BatchColoring:
+                         profile_mask: int = 0, workgroups: int = 0, light: str = "auto",
+                         racy: bool = False) -> BatchColoring:
     """Color many graphs in one launch.  ``rowptr_packed`` (int32[N+G]) and ``colidx_packed``
     (int32[M]) are device tensors in the layout of ``pack_graphs``; ``node_off`` and ``edge_off``
     (G+1 int64 each) are host arrays.  Each graph gets the coloring and round count it gets alone.
@@ -329,7 +332,7 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
     elif out.dtype != torch.int32 or out.numel() != N or not out.is_contiguous() or out.device != dev:
         raise ValueError("out must be a contiguous int32 tensor of N entries on the batch's device")
     call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, N, profile_mask, 0, workgroups,
-                 light)
+                 light, racy)
     rounds = np.full(max(G, 1), -1, dtype=np.int32)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
@@ -367,9 +370,9 @@ class Server:
 
     def __init__(self, node_capacity: int, edge_capacity: int, max_jobs: int = 4096, rounds_per_step: int = 0,
                  mode="hybrid", threshold: int = 0, light_max_degree: int = 0, hub_min_degree: int = 0,
-                 workgroups: int = 0, light: str = "auto"):
-        opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), VALIDATE_DEFAULT, LIGHT[light], None,
-                       int(workgroups), 0)
+                 workgroups: int = 0, light: str = "auto", racy: bool = False):
+        opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), VALIDATE_DEFAULT,
+                       LIGHT[light] | (FLAG_RACY if racy else 0), None, int(workgroups), 0)
         cfg = ServerConfig(int(node_capacity), int(edge_capacity), int(max_jobs), int(rounds_per_step), _mode(mode),
                            0, opts)
         self._h = ctypes.c_void_p()

@@ -193,11 +193,13 @@ int parse_options(const ipgc_options *opt, int mode, Params *p) {
         return fail(IPGC_EINVAL, "hub_min_degree %d must exceed light_max_degree %d", p->hub_min, p->light_max);
     if (o.validate < IPGC_VALIDATE_DEFAULT || o.validate > IPGC_VALIDATE_RANGES)
         return fail(IPGC_EINVAL, "unknown validate level %d", o.validate);
-    if (o.flags & ~(IPGC_FLAG_STEPPED | IPGC_FLAG_LIGHT_PULL | IPGC_FLAG_LIGHT_PUSH))
+    if (o.flags & ~(IPGC_FLAG_STEPPED | IPGC_FLAG_LIGHT_PULL | IPGC_FLAG_LIGHT_PUSH | IPGC_FLAG_RACY))
         return fail(IPGC_EINVAL, "unknown flags 0x%x", o.flags);
     if ((o.flags & IPGC_FLAG_LIGHT_PULL) && (o.flags & IPGC_FLAG_LIGHT_PUSH))
         return fail(IPGC_EINVAL, "IPGC_FLAG_LIGHT_PULL and IPGC_FLAG_LIGHT_PUSH exclude each other");
     p->light = (o.flags & IPGC_FLAG_LIGHT_PULL) ? 1 : (o.flags & IPGC_FLAG_LIGHT_PUSH) ? 0 : -1;
+    p->racy = (o.flags & IPGC_FLAG_RACY) != 0;
+    if (p->racy && p->light < 0) p->light = 1;
     if (o.workgroups < 0) return fail(IPGC_EINVAL, "negative workgroups %d", o.workgroups);
     if (o.reserved != 0) return fail(IPGC_EINVAL, "reserved option field must be 0");
     p->workgroups = o.workgroups;
@@ -305,6 +307,7 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
     const int64_t n_wide = (int64_t)ws.host_ct->class_n[kW] + ws.host_ct->class_n[kM];
     if (P.light == 0 || (P.light < 0 && n_wide > 0)) d.light_pull = kPushAll;
     else d.light_pull = n_wide > 0 ? kPullLight : kPullOnly;
+    d.racy = P.racy ? 1 : 0;
     if (P.check_ids && n_light > 0) {
         TRY(pf.begin(kKindCheck));
         k_check_light<<<(int)std::min<int64_t>(8192, (n_light + kPrepBlock - 1) / kPrepBlock), kPrepBlock, 0, s>>>(d);

@@ -4,6 +4,11 @@
 // of Section IV (a topology-driven sweep or a data-driven worklist pass, picked
 // per round from the worklist size; the worklist is kept in both).
 //
+// Racy mode (optional): a loser writes 0 at once, so a later test in the same
+// step no longer sees its color, and light nodes also avoid their neighbours'
+// visible tentative colors.  The result depends on timing but is a proper
+// coloring: the smallest active id still commits every round.
+//
 // Color state: one int32 per node in the caller's output buffer.
 //   c[v] > 0   v holds committed color c[v];
 //   c[v] <= 0  v is uncolored; after the assign step it holds -t (t >= 1 is its
@@ -180,6 +185,8 @@ struct DevT {
     int32_t sorted;          // every row strictly ascending
     int32_t grid;            // workgroups of the round kernels (segments per class)
     int32_t light_pull;      // kPushAll, kPullLight or kPullOnly: how class L learns its neighbours' colors
+    int32_t racy;            // in-place mode: losers uncolor at once, L assigns avoid in-flight tentatives
+    int32_t pad;
 
     // global id of a neighbour stored in row entry k of node v
     __device__ __forceinline__ int32_t base(int32_t v) const { return gbase ? gbase[v] : 0; }
@@ -698,8 +705,10 @@ __device__ void assign_step(const D &d, const RoundIn &in, Units &un) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) cu[j] = k0 + j < e ? d.c[d.colidx[k0 + j] + gb] : 0;
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (cu[j] > 0 && cu[j] <= 64) used |= 1ull << (cu[j] - 1);
+                for (int j = 0; j < 4; ++j) {
+                    const int32_t x = d.racy ? iabs(cu[j]) : cu[j];  // racy: in-flight tentatives too
+                    if (x > 0 && x <= 64) used |= 1ull << (x - 1);
+                }
             }
             d.c[v] = -__ffsll((unsigned long long)~used);
             un.u[kUPullEntries] += e - b;
@@ -805,7 +814,7 @@ __device__ bool ring_scan_wave(const D &d, int32_t v, int32_t t, int wide, Units
 #pragma unroll
         for (int j = 0; j < kPass; ++j) {
             hit |= u[j] >= 0 && iabs(cu[j]) == t;
-            const bool keep = u[j] >= 0 && cu[j] < 0;
+            const bool keep = u[j] >= 0 && cu[j] <= 0;  // not committed (0: uncolored in place)
             const uint64_t km = __ballot(keep);
             if (keep) {
                 int32_t p = start + len + kept + __popcll(km & lanes_below());
@@ -860,6 +869,7 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
         if (lane == 0) un.u[kUConflictNodes] += 1;
         if (lose) {
             if (lane == 0) {
+                if (d.racy) d.c[v] = 0;
                 const int p = atomicAdd(&s_cnt[q], 1);
                 atomicAdd(&s_deg[q], (unsigned long long)(e - b));
                 os.list[seg_base[q] + p] = v;
@@ -910,6 +920,7 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
         un.u[kUConflictNodes] += 1;
         un.u[kUConflictEntries] += read;
         if (lose) {
+            if (d.racy) d.c[v] = 0;
             const int p = atomicAdd(&s_cnt[kL], 1);
             atomicAdd(&s_deg[kL], (unsigned long long)(e - b));
             os.list[seg_base[kL] + p] = v;

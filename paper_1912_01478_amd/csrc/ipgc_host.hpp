@@ -72,6 +72,7 @@ struct Params {
     int64_t threshold = 0;  // 0: floor(6n/10) for HYBRID
     int workgroups = 0;     // 0: automatic
     int light = -1;         // -1: automatic, 0: push into every byte map, 1: class L pulls
+    bool racy = false;      // in-place (timing-dependent) mode
     int mode = IPGC_MODE_HYBRID;
     ipgc_profile *prof = nullptr;
 };

@@ -477,6 +477,7 @@ SDev Server::dev_view(int64_t nhigh, int64_t threshold) {
     d.sorted = 0;
     d.grid = grid;
     d.light_pull = P.light == 1 ? kPullLight : kPushAll;  // jobs of any class may arrive later
+    d.racy = P.racy ? 1 : 0;
     return d;
 }
 

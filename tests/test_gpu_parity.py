@@ -133,6 +133,28 @@ def test_light_pull_and_push_same_result(g, light):
     assert_parity(g, "data", light=light, stepped=True, light_max_degree=4, hub_min_degree=300)
 
 
+RACY_CASES = [gg.complete(40), gg.star(3000, 0), gg.crown(40), gg.cycle(51), gg.complete_bipartite(40, 1500)] + SMALL
+
+
+@pytest.mark.parametrize("stepped", [False, True])
+@pytest.mark.parametrize("light", ["auto", "push"])
+@pytest.mark.parametrize("g", RACY_CASES, ids=lambda g: g.name)
+def test_racy_mode_is_a_proper_coloring(g, light, stepped):
+    """The optional in-place mode: only validity and the color bound are checked (its result
+    depends on timing).  The round count still cannot exceed n, since the smallest active id
+    commits every round."""
+    import paper_1912_01478_amd as ip
+    rp, ci = torch.from_numpy(g.rowptr).cuda(), torch.from_numpy(g.colidx).cuda()
+    print("[gpu] racy %s light=%s stepped=%s" % (g.name, light, stepped), flush=True)
+    res = ip.color_graph(rp, ci, "hybrid", racy=True, light=light, stepped=stepped, trace=True)
+    col = res.colors.cpu().numpy()
+    P.check_proper(g.rowptr, g.colidx, col)
+    P.check_bounds(g.rowptr, col)
+    assert 1 <= res.rounds <= max(g.n, 1)
+    wl = np.asarray(res.wl_sizes)
+    assert wl[0] == g.n and (np.diff(wl) < 0).all()
+
+
 @pytest.mark.parametrize("g", SMALL[:4], ids=lambda g: g.name)
 def test_unsorted_rows(g):
     """Row order is irrelevant; unsorted rows also switch off the sorted-row early exit."""
