@@ -95,7 +95,7 @@ def parse():
                    help="1: G(10000, 8); 2: R-MAT scale 22 ef 16 (default); 3: road kNN 24M nodes; "
                         "4: batch of 4096 graphs; 5: serving stream")
     p.add_argument("--batch-graphs", type=int, default=4096, help="--config 4: number of graphs")
-    p.add_argument("--mode", default=None, choices=["hybrid", "data", "topology"],
+    p.add_argument("--mode", default=None, choices=["hybrid", "data", "topology", "rebuild"],
                    help="round schedule (default: the tuned one for the workload's class, else hybrid)")
     p.add_argument("--light", default=None, choices=["auto", "pull", "push"],
                    help="how light nodes learn their neighbours' colors (default: tuned, else auto)")
@@ -463,7 +463,7 @@ def main():
     modes = {}
     if args.compare_steps > 0:
         # each schedule with the other options as chosen (and, if tuned, the library defaults)
-        for other in ("hybrid", "data", "topology"):
+        for other in ("hybrid", "data", "topology", "rebuild"):
             okw = dict(kw, mode=other, threshold=0)
             oms, _, ores = time_steps(torch, w, okw, args.compare_steps, 1)
             assert w.rounds(ores) == rounds

@@ -55,11 +55,15 @@ typedef enum ipgc_status {
 /* Round schedules (Section IV).  TOPOLOGY runs every round as a sweep over all
  * nodes, DATA runs every round over the worklist, HYBRID picks per round with
  * the threshold H.  All three push the nodes that lose a conflict onto the
- * worklist, and all three give the same colors and round count. */
+ * worklist.  REBUILD is the discard-and-rebuild hybrid the paper contrasts
+ * its own with (Section I): rounds are picked as for HYBRID, but sweeps keep
+ * no worklist, and the first data-driven round after sweeps rebuilds it by
+ * scanning every node.  All four give the same colors and round count. */
 typedef enum ipgc_mode {
     IPGC_MODE_TOPOLOGY = 0,
     IPGC_MODE_DATA = 1,
-    IPGC_MODE_HYBRID = 2
+    IPGC_MODE_HYBRID = 2,
+    IPGC_MODE_REBUILD = 3
 } ipgc_mode;
 
 /* Validation levels.  A column id outside [0, n) would make the kernels read

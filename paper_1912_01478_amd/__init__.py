@@ -20,7 +20,8 @@ LIB_PATH = os.environ.get("IPGC_LIBRARY") or os.path.join(HERE, "libipgc.so")
 MODE_TOPOLOGY = 0
 MODE_DATA = 1
 MODE_HYBRID = 2
-MODES = {"topology": MODE_TOPOLOGY, "data": MODE_DATA, "hybrid": MODE_HYBRID}
+MODE_REBUILD = 3
+MODES = {"topology": MODE_TOPOLOGY, "data": MODE_DATA, "hybrid": MODE_HYBRID, "rebuild": MODE_REBUILD}
 
 VALIDATE_DEFAULT = 0
 VALIDATE_NONE = 1

@@ -23,7 +23,7 @@ KNOBS = {
     "workgroups": [0, 64, 128, 256, 384, 512],
     "light_max_degree": [0, 8, 16],
     "hub_min_degree": [0, 256, 4096, 16384],
-    "schedule": ["hybrid", "data", "hybrid_h2", "hybrid_h10", "topology"],
+    "schedule": ["hybrid", "data", "hybrid_h2", "hybrid_h10", "topology", "rebuild"],
     "light": ["auto", "pull", "push"],
 }
 DEFAULT = {"workgroups": 0, "light_max_degree": 0, "hub_min_degree": 0, "schedule": "hybrid", "light": "auto"}
@@ -34,7 +34,7 @@ DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_
 def schedule_args(schedule: str, n: int) -> dict:
     """Mode and threshold of a schedule name: "hybrid" (H = floor(6n/10)), "hybrid_hK" (H = floor(K n/100),
     i.e. topology-driven rounds only while more than K% of the nodes are active), "data", "topology"."""
-    if schedule in ("hybrid", "data", "topology"):
+    if schedule in ("hybrid", "data", "topology", "rebuild"):
         return {"mode": schedule, "threshold": 0}
     if schedule.startswith("hybrid_h"):
         pct = int(schedule[len("hybrid_h"):])

@@ -180,7 +180,7 @@ int cooperative_capacity(Workspace &ws, int dev, int *out) {
 }  // namespace
 
 int parse_options(const ipgc_options *opt, int mode, Params *p) {
-    if (mode != IPGC_MODE_TOPOLOGY && mode != IPGC_MODE_DATA && mode != IPGC_MODE_HYBRID)
+    if (mode != IPGC_MODE_TOPOLOGY && mode != IPGC_MODE_DATA && mode != IPGC_MODE_HYBRID && mode != IPGC_MODE_REBUILD)
         return fail(IPGC_EINVAL, "unknown mode %d", mode);
     ipgc_options o{};
     if (opt) o = *opt;
@@ -252,7 +252,7 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
     int64_t H;
     if (P.mode == IPGC_MODE_TOPOLOGY) H = -1;          // |WL| > -1 always holds
     else if (P.mode == IPGC_MODE_DATA) H = INT64_MAX;  // never
-    else H = P.threshold > 0 ? P.threshold : (6 * n) / 10;
+    else H = P.threshold > 0 ? P.threshold : (6 * n) / 10;  // HYBRID and REBUILD
 
     d.cls = ws.cls.p;
     d.F = ws.F.p;
@@ -308,6 +308,7 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
     if (P.light == 0 || (P.light < 0 && n_wide > 0)) d.light_pull = kPushAll;
     else d.light_pull = n_wide > 0 ? kPullLight : kPullOnly;
     d.racy = P.racy ? 1 : 0;
+    d.discard = P.mode == IPGC_MODE_REBUILD ? 1 : 0;
     if (P.check_ids && n_light > 0) {
         TRY(pf.begin(kKindCheck));
         k_check_light<<<(int)std::min<int64_t>(8192, (n_light + kPrepBlock - 1) / kPrepBlock), kPrepBlock, 0, s>>>(d);
@@ -337,6 +338,7 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
         TRY(read_counters(ws, s));
     } else {
         for (int32_t r = 1; r <= n + 1; ++r) {
+            if (d.discard) k_rebuild_round<<<grid, kRoundBlock, 0, s>>>(d, r);
             TRY(pf.begin(kKindAssign));
             k_assign_round<<<grid, kRoundBlock, 0, s>>>(d, r);
             TRY(pf.end(kKindAssign));

@@ -131,7 +131,8 @@ struct Counters {
     int32_t bad_ids;
     int32_t unsorted;
     int32_t hub_winners;              // hubs committed in the current round
-    int32_t pad[2];
+    int32_t prev_discarded;           // the last round kept no worklist (discard mode, stepped launches)
+    int32_t pad;
 };
 
 // A committed hub waiting for the push step.
@@ -186,7 +187,7 @@ struct DevT {
     int32_t grid;            // workgroups of the round kernels (segments per class)
     int32_t light_pull;      // kPushAll, kPullLight or kPullOnly: how class L learns its neighbours' colors
     int32_t racy;            // in-place mode: losers uncolor at once, L assigns avoid in-flight tentatives
-    int32_t pad;
+    int32_t discard;         // topology-driven rounds keep no worklist; it is rebuilt when data rounds start
 
     // global id of a neighbour stored in row entry k of node v
     __device__ __forceinline__ int32_t base(int32_t v) const { return gbase ? gbase[v] : 0; }
@@ -319,6 +320,18 @@ __device__ __forceinline__ int block_scan(int x, int *total) {
     *total = s_wave[31];
     __syncthreads();
     return excl;
+}
+
+// Ordered append of the flagged threads of the workgroup: returns each flagged
+// thread's position after *count and advances *count (shared) by the total.
+__device__ __forceinline__ int block_append(bool flag, int *count) {
+    int tot;
+    const int ex = block_scan(flag ? 1 : 0, &tot);
+    const int base = *count;
+    __syncthreads();
+    if (threadIdx.x == 0) *count = base + tot;
+    __syncthreads();
+    return base + ex;
 }
 
 // Initial state (Section II-C: every node starts uncolored, every node is in
@@ -850,6 +863,7 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
         s_deg[threadIdx.x] = 0;
     }
     __syncthreads();
+    const bool discard = d.discard && in.topo;  // discard mode: a sweep keeps only the losers' count
     const int32_t seg_base[kNumClasses] = {os.cls_off[kL] + (int32_t)blockIdx.x * os.cap[kL],
                                            os.cls_off[kW] + (int32_t)blockIdx.x * os.cap[kW],
                                            os.cls_off[kM] + (int32_t)blockIdx.x * os.cap[kM]};
@@ -872,7 +886,7 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
                 if (d.racy) d.c[v] = 0;
                 const int p = atomicAdd(&s_cnt[q], 1);
                 atomicAdd(&s_deg[q], (unsigned long long)(e - b));
-                os.list[seg_base[q] + p] = v;
+                if (!discard) os.list[seg_base[q] + p] = v;
             }
         } else {
             if (lane == 0) {
@@ -923,7 +937,7 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
             if (d.racy) d.c[v] = 0;
             const int p = atomicAdd(&s_cnt[kL], 1);
             atomicAdd(&s_deg[kL], (unsigned long long)(e - b));
-            os.list[seg_base[kL] + p] = v;
+            if (!discard) os.list[seg_base[kL] + p] = v;
         } else {
             d.c[v] = t;
             un.u[kUCommits] += 1;
@@ -1053,7 +1067,10 @@ __device__ void round_record(const D &d, int r, const RoundIn &in, bool reset_hu
             d.trace[r - 1] = in.total;
             d.trace_deg[r - 1] = dsum;
         }
-        if (reset_hubs) d.ct->hub_winners = 0;
+        if (reset_hubs) {
+            d.ct->hub_winners = 0;
+            d.ct->prev_discarded = d.discard && in.topo;
+        }
     }
 }
 
@@ -1076,6 +1093,43 @@ __device__ __forceinline__ void tick(const D &d, int64_t i) {
     if (blockIdx.x == 0 && threadIdx.x == 0 && i < d.tick_cap) d.ticks[i] = wall_clock64();
 }
 
+// Discard mode, first data-driven round after sweeps: rebuild the worklist
+// (list `par`) from the static lists.  Workgroup b takes items
+// [b*span_k, (b+1)*span_k) of class k and appends its uncolored nodes, in
+// order, to its own segment.
+template <class D>
+__device__ void rebuild_step(const D &d, int par) {
+    __shared__ int s_cnt;
+    __shared__ unsigned long long s_deg;
+    const int b = blockIdx.x, nb = gridDim.x;
+    for (int k = 0; k < kNumClasses; ++k) {
+        if (threadIdx.x == 0) {
+            s_cnt = 0;
+            s_deg = 0;
+        }
+        __syncthreads();
+        const int32_t total = d.ct->class_n[k];
+        const int32_t *list = d.static_list + d.ct->static_off[k];
+        const int64_t span = ((int64_t)total + nb - 1) / nb, lo = (int64_t)b * span, hi = min<int64_t>(lo + span, total);
+        int32_t *seg = d.seg_list[par] + d.ct->seg_off[k] + (int64_t)b * d.ct->seg_cap[k];
+        for (int64_t c0 = lo; c0 < hi; c0 += blockDim.x) {
+            const int64_t i = c0 + threadIdx.x;
+            const int32_t v = i < hi ? list[i] : 0;
+            const bool act = i < hi && d.c[v] <= 0;
+            const int64_t ds = wave_sum(act ? d.rowptr[v + 1] - d.rowptr[v] : 0);
+            if (lane_id() == 0 && ds) atomicAdd(&s_deg, (unsigned long long)ds);
+            const int p = block_append(act, &s_cnt);
+            if (act) seg[p] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            d.seg_cnt[par][k * nb + b] = s_cnt;
+            d.seg_deg[par][k * nb + b] = (int64_t)s_deg;
+        }
+        __syncthreads();
+    }
+}
+
 // Rounds first .. last (or until the worklist is empty) in one cooperative
 // launch: assign | barrier | conflict | barrier [| hub push | barrier].  Every
 // workgroup reads the same counts after each barrier, so all take the same
@@ -1088,9 +1142,17 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
     gb.setup(d.bar);
     Units un;
     int32_t r = first;
+    bool discarded = false;  // the previous round kept no worklist
     for (; r <= last; ++r) {
         if (r > 1) load_segments(d, r & 1, pre);
-        const RoundIn in = round_view(d, r, pre);
+        RoundIn in = round_view(d, r, pre);
+        if (discarded && !in.topo && in.total > 0) {
+            rebuild_step(d, r & 1);
+            gb.sync();
+            load_segments(d, r & 1, pre);
+            in = round_view(d, r, pre);
+        }
+        discarded = d.discard && in.topo;
         if (blockIdx.x == 0) round_record(d, r, in, false);
         if (in.total == 0) break;
         tick(d, 3 * (int64_t)(r - 1));
@@ -1116,6 +1178,17 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
 
 // The same steps as separate launches (the launch boundary is the barrier),
 // for hosts that cannot launch cooperatively and for per-step timing.
+// Stepped launches, discard mode: the rebuild of round r when round r - 1 kept no worklist.
+template <class D>
+__global__ __launch_bounds__(kRoundBlock) void k_rebuild_round(D d, int32_t r) {
+    if (d.ct->finished || r == 1 || !d.ct->prev_discarded) return;
+    __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
+    load_segments(d, r & 1, pre);
+    const RoundIn in = round_view(d, r, pre);
+    if (in.topo || in.total == 0) return;
+    rebuild_step(d, r & 1);
+}
+
 template <class D>
 __global__ __launch_bounds__(kRoundBlock) void k_assign_round(D d, int32_t r) {
     if (d.ct->finished) return;

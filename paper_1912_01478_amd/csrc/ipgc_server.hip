@@ -137,18 +137,6 @@ __global__ __launch_bounds__(256) void k_srv_retire(int8_t *cls, int32_t v0, int
         cls[v0 + i] = kNoNode;
 }
 
-// Ordered append of the flagged threads of the workgroup: returns each flagged
-// thread's position after *count and advances *count (shared) by the total.
-__device__ __forceinline__ int block_append(bool flag, int *count) {
-    int tot;
-    const int ex = block_scan(flag ? 1 : 0, &tot);
-    const int base = *count;
-    __syncthreads();
-    if (threadIdx.x == 0) *count = base + tot;
-    __syncthreads();
-    return base + ex;
-}
-
 // Workgroup b of the round grid takes node slots [b*span, (b+1)*span): its
 // uncolored nodes of each class go, in ascending order, to its own segment of
 // list `par` (the list the next round reads), with their degree sums; its
@@ -478,6 +466,7 @@ SDev Server::dev_view(int64_t nhigh, int64_t threshold) {
     d.grid = grid;
     d.light_pull = P.light == 1 ? kPullLight : kPushAll;  // jobs of any class may arrive later
     d.racy = P.racy ? 1 : 0;
+    d.discard = P.mode == IPGC_MODE_REBUILD ? 1 : 0;
     return d;
 }
 

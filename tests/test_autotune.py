@@ -58,7 +58,7 @@ def test_search_finds_the_cheapest_point():
     cost = {"workgroups": {0: 5, 64: 3, 128: 1, 256: 2, 384: 4, 512: 6},
             "light_max_degree": {0: 1, 8: 3, 16: 2},
             "hub_min_degree": {0: 2, 256: 1, 4096: 3, 16384: 4},
-            "schedule": {"hybrid": 2, "data": 1, "hybrid_h2": 1.5, "hybrid_h10": 3, "topology": 9},
+            "schedule": {"hybrid": 2, "data": 1, "hybrid_h2": 1.5, "hybrid_h10": 3, "topology": 9, "rebuild": 2.5},
             "light": {"auto": 1, "pull": 0.5, "push": 2}}
     inv = {}
 
@@ -68,7 +68,7 @@ def test_search_finds_the_cheapest_point():
     def timer(fn, steps, warmup):
         fn(None)
         kw = inv["kw"]
-        sched = {("data", 0): "data", ("topology", 0): "topology", ("hybrid", 0): "hybrid",
+        sched = {("data", 0): "data", ("topology", 0): "topology", ("hybrid", 0): "hybrid", ("rebuild", 0): "rebuild",
                  ("hybrid", 20): "hybrid_h2", ("hybrid", 100): "hybrid_h10"}[(kw["mode"], kw["threshold"])]
         hub = kw["hub_min_degree"] if kw["hub_min_degree"] in cost["hub_min_degree"] else 0
         return 10.0 + cost["workgroups"][kw["workgroups"]] + cost["light_max_degree"][kw["light_max_degree"]] \

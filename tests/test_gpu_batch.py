@@ -13,7 +13,7 @@ from tests import _props as P
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-MODES = ("topology", "data", "hybrid")
+MODES = ("topology", "data", "hybrid", "rebuild")
 
 
 @pytest.fixture(scope="module", autouse=True)

@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-MODES = ("topology", "data", "hybrid")
+MODES = ("topology", "data", "hybrid", "rebuild")
 
 
 def gpu(g, mode="hybrid", rowptr=None, colidx=None, **kw):
@@ -105,8 +105,8 @@ SMALL = small_graphs()
 def test_random_parity(g, mode):
     ref = oracle.color_graph(g.rowptr, g.colidx)
     col, rounds, _, topo = assert_parity(g, mode, ref=ref)
-    expect_topo = {"topology": [1] * rounds, "data": [0] * rounds,
-                   "hybrid": [int(w > (6 * g.n) // 10) for w in ref.wl_sizes]}[mode]
+    hybrid = [int(w > (6 * g.n) // 10) for w in ref.wl_sizes]
+    expect_topo = {"topology": [1] * rounds, "data": [0] * rounds, "hybrid": hybrid, "rebuild": hybrid}[mode]
     assert topo == expect_topo
 
 

@@ -66,7 +66,7 @@ def _server(mode="hybrid", nodes=4_000_000, edges=40_000_000, **kw):
     return ip.Server(nodes, edges, mode=mode, **kw)
 
 
-@pytest.mark.parametrize("mode", ["topology", "data", "hybrid"])
+@pytest.mark.parametrize("mode", ["topology", "data", "hybrid", "rebuild"])
 def test_all_at_once_matches_oracle(mode):
     with _server(mode) as srv:
         ids = {srv.submit(g.rowptr, g.colidx): g for g in MIX}
