@@ -117,6 +117,8 @@ def parse():
     p.add_argument("--loads", default="0.5,0.8", help="--config 5: arrival rates as fractions of the saturated rate")
     p.add_argument("--pinned", action="store_true",
                    help="--config 5: keep the job stream in pinned host memory (uploads at full PCIe speed)")
+    p.add_argument("--push-microbench", type=int, default=0, metavar="N",
+                   help="run only the worklist push micro-benchmark on N node ids (Section III) and print its summary")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="also run one plain device copy of this many MiB (a reference for HBM byte counters)")
     return p.parse_args()
@@ -364,6 +366,39 @@ def main_serving(args, pkg, gg, np):
     print(json.dumps(line), flush=True)
 
 
+def main_push_microbench(args, pkg, np):
+    """Push_WL vs Push_NoWL (Section III): time per iteration, crossover, and the worklist fraction
+    at which iterating over the worklist starts to win (a device-specific reading of H)."""
+    n, count = args.push_microbench, 1000
+    runs = {}
+    for atomic in (False, True):
+        for nowl in (False, True):
+            name = ("Push_NoWL" if nowl else "Push_WL") + ("_atomic" if atomic else "_segmented")
+            tti, sizes = pkg.push_microbench(n, count, nowl=nowl, atomic=atomic)
+            runs[name] = (tti, sizes)
+            log("%s: %d iterations, total %.1f ms, first %.2f us, last %.2f us" % (
+                name, len(tti), tti.sum() / 1000, tti[0], tti[-1]))
+    out = {"metric": "worklist push micro-benchmark (time per iteration)", "n": n, "count": count, "variants": {}}
+    for push in ("segmented", "atomic"):
+        wl, nowl = runs["Push_WL_" + push][0], runs["Push_NoWL_" + push][0]
+        sizes = runs["Push_WL_" + push][1]
+        k = min(len(wl), len(nowl))
+        # smoothed comparison (window of 101 iterations), then the first iteration where WL wins
+        w = 101
+        sm_wl = np.convolve(wl[:k], np.ones(w) / w, mode="same")
+        sm_nowl = np.convolve(nowl[:k], np.ones(w) / w, mode="same")
+        wins = np.nonzero(sm_wl < sm_nowl)[0]
+        cross = int(wins[0]) if wins.size else None
+        ideal = float(np.minimum(wl[:k], nowl[:k]).sum())
+        out["variants"][push] = {
+            "push_wl_total_ms": round(float(wl.sum()) / 1000, 3), "push_nowl_total_ms": round(float(nowl.sum()) / 1000, 3),
+            "ideal_hybrid_ms": round(ideal / 1000, 3), "crossover_iteration": cross,
+            "crossover_wl_fraction": round(float(sizes[cross]) / n, 4) if cross is not None else None,
+            "tti_us_samples": {str(i): [round(float(wl[i]), 2), round(float(nowl[i]), 2)]
+                               for i in sorted(set([0, 1, k // 4, k // 2, 3 * k // 4, k - 1] + ([cross] if cross else [])))}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -395,6 +430,8 @@ def main():
         print("bench.py: no HIP device", file=sys.stderr)
         sys.exit(1)
 
+    if args.push_microbench:
+        return main_push_microbench(args, pkg, np)
     if args.config == 5:
         return main_serving(args, pkg, gg, np)
     t = time.time()

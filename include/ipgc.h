@@ -289,6 +289,25 @@ int ipgc_server_stats_get(const ipgc_server *server, ipgc_server_stats *stats);
 /* Frees the arena.  Queued and resident jobs are dropped. */
 void ipgc_server_destroy(ipgc_server *server);
 
+/*
+ * Worklist push micro-benchmark (Section III, Listings 1 and 2): starting from
+ * a worklist of all n node ids, iteration i deactivates ids [count*i,
+ * count*(i+1)) and pushes the rest into the next worklist, iterating over the
+ * worklist (nowl = 0: Push_WL) or over every id (nowl = 1: Push_NoWL), until
+ * the worklist is empty.  atomic = 0 pushes with per-workgroup segments and no
+ * global atomic (as the coloring kernels do); atomic = 1 fills one global
+ * worklist with one atomicAdd per wavefront.  One cooperative launch with a
+ * grid barrier per iteration.  HOST arrays of `capacity` entries (at least
+ * ceil(n/count) + 2) receive the device wall clock at the start of every
+ * iteration plus one at the end (ticks) and the worklist size at the start of
+ * every iteration (sizes); iterations receives the number of non-empty
+ * iterations and tick_khz the rate of the clock.  Runs on the current device
+ * and blocks until done.  The time per iteration i is
+ * (ticks[i+1] - ticks[i]) / tick_khz milliseconds.
+ */
+int ipgc_push_microbench(int64_t n, int32_t count, int32_t nowl, int32_t atomic, uint64_t *ticks, int32_t *sizes,
+                         int64_t capacity, int64_t *iterations, int64_t *tick_khz);
+
 /* Message for the last failing call on this thread ("" if none).  Valid until
  * the next call on the same thread. */
 const char *ipgc_last_error(void);

@@ -34,7 +34,7 @@ STATUS = {0: "IPGC_OK", -1: "IPGC_EINVAL", -2: "IPGC_ETOOBIG", -3: "IPGC_EBADCSR
 EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_color_graphs_batched", "ipgc_last_error",
            "ipgc_kernel_name", "ipgc_unit_name", "ipgc_version", "ipgc_release_workspaces", "ipgc_server_create",
            "ipgc_server_submit", "ipgc_server_step", "ipgc_server_poll", "ipgc_server_stats_get",
-           "ipgc_server_destroy")
+           "ipgc_server_destroy", "ipgc_push_microbench")
 FLAG_STEPPED = 1
 FLAG_LIGHT_PULL = 2
 FLAG_LIGHT_PUSH = 4
@@ -136,6 +136,9 @@ def library() -> ctypes.CDLL:
         lib.ipgc_server_stats_get.argtypes = [srv, ctypes.POINTER(ServerStats)]
         lib.ipgc_server_destroy.restype = None
         lib.ipgc_server_destroy.argtypes = [srv]
+        lib.ipgc_push_microbench.restype = i32
+        lib.ipgc_push_microbench.argtypes = [i64, i32, i32, i32, vp, vp, i64, ctypes.POINTER(ctypes.c_int64),
+                                             ctypes.POINTER(ctypes.c_int64)]
         lib.ipgc_last_error.restype = ctypes.c_char_p
         lib.ipgc_last_error.argtypes = []
         lib.ipgc_kernel_name.restype = ctypes.c_char_p
@@ -345,6 +348,26 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
             ctypes.c_void_p(out.data_ptr() if N else 0), rounds.ctypes.data_as(ctypes.c_void_p), call.trace_ref())
     _check(rc)
     return call.finish(BatchColoring(out, rounds[:G].tolist(), node_off))
+
+
+def push_microbench(n: int, count: int = 1000, nowl: bool = False, atomic: bool = False):
+    """Worklist push micro-benchmark (``ipgc_push_microbench``) on the current device.  Returns
+    (tti_us, sizes): the time of every non-empty iteration in microseconds and the worklist size
+    at its start."""
+    import numpy as np
+    import torch  # noqa: F401  (the device context belongs to torch's current device)
+
+    cap = (n + count - 1) // count + 2
+    ticks = np.zeros(cap, dtype=np.uint64)
+    sizes = np.zeros(cap, dtype=np.int32)
+    iters = ctypes.c_int64(0)
+    khz = ctypes.c_int64(0)
+    _check(library().ipgc_push_microbench(int(n), int(count), int(bool(nowl)), int(bool(atomic)),
+                                          ticks.ctypes.data_as(ctypes.c_void_p), sizes.ctypes.data_as(ctypes.c_void_p),
+                                          cap, ctypes.byref(iters), ctypes.byref(khz)))
+    k = iters.value
+    tti = np.diff(ticks[:k + 1].astype(np.float64)) / khz.value * 1000.0
+    return tti, sizes[:k].copy()
 
 
 # ---------------------------------------------------------------- serving
