@@ -318,15 +318,21 @@ def main_serving(args, pkg, gg, np):
     J, M = pb.num_graphs, int(pb.edge_off[-1])
     avg_degree = M / max(1, int(pb.node_off[-1]))
     log("generated %d jobs, N=%d M=%d in %.1fs" % (J, pb.node_off[-1], M, time.time() - t))
+    host_memory = "pageable"
     if args.pinned:
         import torch
         t = time.time()
-        rp = torch.empty(pb.rowptr_packed.size, dtype=torch.int32, pin_memory=True)
-        ci = torch.empty(pb.colidx_packed.size, dtype=torch.int32, pin_memory=True)
-        rp.numpy()[:] = pb.rowptr_packed
-        ci.numpy()[:] = pb.colidx_packed
-        pb.rowptr_packed, pb.colidx_packed = rp.numpy(), ci.numpy()
-        log("job stream copied to pinned host memory in %.1fs" % (time.time() - t))
+        try:
+            rp = torch.empty(pb.rowptr_packed.size, dtype=torch.int32, pin_memory=True)
+            ci = torch.empty(pb.colidx_packed.size, dtype=torch.int32, pin_memory=True)
+            rp.numpy()[:] = pb.rowptr_packed
+            ci.numpy()[:] = pb.colidx_packed
+            pb.rowptr_packed, pb.colidx_packed = rp.numpy(), ci.numpy()
+            host_memory = "pinned"
+            log("job stream copied to pinned host memory in %.1fs" % (time.time() - t))
+        except RuntimeError as e:  # the host may not pin that much memory
+            host_memory = "pageable (pinning %.1f GB failed)" % ((pb.rowptr_packed.nbytes + pb.colidx_packed.nbytes) / 1e9)
+            log("pinning the job stream failed (%s); keeping pageable memory" % str(e).splitlines()[0])
     runs = {}
     wall, lat, st = serve(pkg, pb, np.zeros(J), args, avg_degree)
     sat_jobs = J / wall
@@ -358,7 +364,7 @@ def main_serving(args, pkg, gg, np):
         "config": {"workload": "serving_%djobs_c4mix_10pct_rmat_s20" % J, "jobs": J, "n": int(pb.node_off[-1]), "m": M,
                    "budget_gb": args.budget_gb, "arena_nodes": nodes, "arena_edges": edges,
                    "rounds_per_step": args.rounds_per_step, "mode": "hybrid", "parallelism": "single-gpu",
-                   "headline_run": key, "host_memory": "pinned" if args.pinned else "pageable",
+                   "headline_run": key, "host_memory": host_memory,
                    "uploads": "timed (jobs arrive as host CSR)"},
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "runs": runs, "roofline": None, "cpu_baseline": None,
