@@ -105,11 +105,11 @@ typedef struct ipgc_profile {
 typedef struct ipgc_options {
     int64_t threshold;         /* H for HYBRID (topology round iff |WL| > H); 0 or less: floor(6n/10), the
                                   paper's 60% of the node count.  Ignored by TOPOLOGY and DATA. */
-    int32_t light_max_degree;  /* nodes with degree <= this run a thread each and read their
-                                  neighbours' colors every round (1..32; 0: default 32) */
-    int32_t hub_min_degree;    /* nodes with degree above this are hubs: their conflict scans run a
-                                  workgroup each, and neighbours read hub colors instead of hubs
-                                  writing them out (> light_max_degree; 0: default 1024) */
+    int32_t light_max_degree;  /* nodes with degree <= this run a thread each; the others a wavefront
+                                  each (1..32; 0: default 32) */
+    int32_t hub_min_degree;    /* nodes with degree above this are hubs: when one commits, the whole
+                                  grid writes its color into its neighbours' byte maps in a separate
+                                  step of the round (> light_max_degree; 0: default 1024) */
     int32_t validate;          /* IPGC_VALIDATE_* */
     int32_t flags;             /* IPGC_FLAG_* */
     ipgc_profile *profile;     /* optional per-kernel timing and work counts (NULL: none) */
@@ -233,8 +233,9 @@ typedef struct ipgc_server_config {
     int32_t mode;             /* ipgc_mode of the rounds */
     int32_t reserved;         /* must be 0 */
     ipgc_options options;     /* threshold (0: floor(6N/10) over the resident nodes), light_max_degree,
-                                 hub_min_degree, workgroups; validate must not be IPGC_VALIDATE_NONE
-                                 (every admitted job is checked); flags and profile must be 0 */
+                                 hub_min_degree, workgroups, IPGC_FLAG_LIGHT_PULL / _PUSH / _RACY;
+                                 validate must not be IPGC_VALIDATE_NONE (every admitted job is
+                                 checked); IPGC_FLAG_STEPPED and a profile are rejected */
 } ipgc_server_config;
 
 /* Outcome of a finished job. */
