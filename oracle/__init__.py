@@ -17,6 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ipgc_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "bfs_oracle.c")]
 _LIB = os.path.join(_HERE, "libipgc_oracle.so")
 _lib = None
 
@@ -25,9 +26,9 @@ _I32P = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain C, no OpenMP: it is single-threaded by design)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, _SRC])
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp] + _SRCS)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -41,6 +42,8 @@ def _load():
         lib.ipgc_oracle_color.restype = ctypes.c_int
         lib.ipgc_oracle_color.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, vp, vp, vp,
                                           ctypes.c_int64, vp, vp, vp, ctypes.c_int64]
+        lib.ipgc_oracle_bfs.restype = ctypes.c_int
+        lib.ipgc_oracle_bfs.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, vp, vp, ctypes.c_int64, vp]
         lib.ipgc_oracle_first_free_color.restype = ctypes.c_int32
         lib.ipgc_oracle_first_free_color.argtypes = [_I32P, _I32P, ctypes.c_int64, _I32P, ctypes.c_int64]
         _lib = lib
@@ -107,3 +110,25 @@ def algorithmic_bytes(res: OracleResult) -> int:
     worklist entry 4 + row bounds 8 + own tentative 4 + commit-or-push 4 (conflict) = 36.
     Per neighbour visit: column index 4 + neighbour color 4, once in each step = 16."""
     return int(36 * res.wl_sizes.sum() + 16 * res.wl_degree_sums.sum())
+
+
+@dataclass
+class BfsResult:
+    dist: np.ndarray      # int32[n]: hops from the source, -1 if unreachable
+    levels: int           # non-empty frontiers (largest finite distance + 1)
+    frontier_sizes: np.ndarray  # int64[levels]: nodes at each distance
+
+
+def bfs(rowptr, colidx, source: int) -> BfsResult:
+    """Breadth-first search by its definition (FIFO queue): hop distances from `source`."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    colidx = np.ascontiguousarray(colidx, dtype=np.int32)
+    n = rowptr.size - 1
+    dist = np.empty(max(n, 0), dtype=np.int32)
+    sizes = np.zeros(max(n, 1), dtype=np.int64)
+    levels = ctypes.c_int32(0)
+    rc = _load().ipgc_oracle_bfs(rowptr.ctypes.data, colidx.ctypes.data, n, int(source), dist.ctypes.data,
+                                 sizes.ctypes.data, sizes.size, ctypes.byref(levels))
+    if rc != 0:
+        raise ValueError("oracle bfs failed (%d)" % rc)
+    return BfsResult(dist, levels.value, sizes[:levels.value].copy())
