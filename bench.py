@@ -117,6 +117,8 @@ def parse():
     p.add_argument("--loads", default="0.5,0.8", help="--config 5: arrival rates as fractions of the saturated rate")
     p.add_argument("--pinned", action="store_true",
                    help="--config 5: keep the job stream in pinned host memory (uploads at full PCIe speed)")
+    p.add_argument("--bfs", action="store_true",
+                   help="run only BFS under the keep-worklist hybrid on the config's graph (from its highest-degree node)")
     p.add_argument("--push-microbench", type=int, default=0, metavar="N",
                    help="run only the worklist push micro-benchmark on N node ids (Section III) and print its summary")
     p.add_argument("--copy-mib", type=int, default=0,
@@ -372,6 +374,35 @@ def main_serving(args, pkg, gg, np):
     print(json.dumps(line), flush=True)
 
 
+def main_bfs(args, pkg, gg, np, torch):
+    """BFS with the keep-the-worklist hybrid and the three schedules: traversed entries per second."""
+    g = gg.config_graph(args.config)
+    deg = np.diff(g.rowptr)
+    source = int(np.argmax(deg))
+    rp, ci = torch.from_numpy(g.rowptr).cuda(), torch.from_numpy(g.colidx).cuda()
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    res = pkg.bfs(rp, ci, source, out=out, trace=True)
+    reached = out >= 0
+    m_reached = int(torch.diff(rp.long())[reached].sum().item())
+    modes = {}
+    for mode in ("hybrid", "data", "topology"):
+        for _ in range(args.warmup):
+            pkg.bfs(rp, ci, source, mode, out=out, validate=pkg.VALIDATE_NONE)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            pkg.bfs(rp, ci, source, mode, out=out, validate=pkg.VALIDATE_NONE)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        modes[mode] = {"ms": round(ms, 4), "traversed_entries_per_s": m_reached / (ms / 1000.0)}
+        log("bfs %s: %.3f ms" % (mode, ms))
+    print(json.dumps({"metric": "BFS traversed CSR entries per second (keep-worklist hybrid)", "workload": g.name,
+                      "source": source, "levels": res.levels, "reached": int(reached.sum().item()),
+                      "m_reached": m_reached, "frontier_sizes": res.frontier_sizes, "modes": modes}), flush=True)
+
+
 def main_push_microbench(args, pkg, np):
     """Push_WL vs Push_NoWL (Section III): time per iteration, crossover, and the worklist fraction
     at which iterating over the worklist starts to win (a device-specific reading of H)."""
@@ -438,6 +469,8 @@ def main():
 
     if args.push_microbench:
         return main_push_microbench(args, pkg, np)
+    if args.bfs:
+        return main_bfs(args, pkg, gg, np, torch)
     if args.config == 5:
         return main_serving(args, pkg, gg, np)
     t = time.time()

@@ -291,6 +291,26 @@ int ipgc_server_stats_get(const ipgc_server *server, ipgc_server_stats *stats);
 void ipgc_server_destroy(ipgc_server *server);
 
 /*
+ * Breadth-first search under the same keep-the-worklist hybrid schedule (the
+ * paper's driver applied to another worklist algorithm, as its conclusion
+ * proposes).  Level L expands the nodes at distance L, either by a sweep over
+ * all nodes (topology-driven, iff the frontier holds more than H nodes; by
+ * default H = floor(6n/10)) or by walking the worklist (data-driven); both
+ * kinds push every newly reached node onto the next worklist.
+ *
+ * csr_rowptr, csr_colidx  DEVICE, the CSR of ipgc_color_graph (read only).
+ * source      the start node, in [0, n).
+ * mode        IPGC_MODE_TOPOLOGY, _DATA or _HYBRID (REBUILD is rejected).
+ * options     threshold, workgroups and validate are used (NULL: defaults); flags must be 0.
+ * out_dist    DEVICE, n int32: hops from the source, -1 if unreachable.
+ * out_levels  HOST: the number of non-empty frontiers (the largest finite distance + 1).
+ * trace       optional: the frontier size of every level and its kind.
+ * Blocks until done; returns the ipgc_color_graph error codes.
+ */
+int ipgc_bfs(const int32_t *csr_rowptr, const int32_t *csr_colidx, int64_t n, int64_t m, int64_t source, int mode,
+             const ipgc_options *options, void *stream, int32_t *out_dist, int32_t *out_levels, ipgc_trace *trace);
+
+/*
  * Worklist push micro-benchmark (Section III, Listings 1 and 2): starting from
  * a worklist of all n node ids, iteration i deactivates ids [count*i,
  * count*(i+1)) and pushes the rest into the next worklist, iterating over the
@@ -322,8 +342,8 @@ const char *ipgc_unit_name(int kind);
 /* ABI version: (major << 16) | minor. */
 int ipgc_version(void);
 
-/* Releases the cached per-device workspaces.  Optional; safe to call anytime
- * no other call is in flight. */
+/* Releases the cached per-device workspaces (of the coloring and BFS entry
+ * points).  Optional; safe to call anytime no other call is in flight. */
 void ipgc_release_workspaces(void);
 
 #ifdef __cplusplus

@@ -34,7 +34,7 @@ STATUS = {0: "IPGC_OK", -1: "IPGC_EINVAL", -2: "IPGC_ETOOBIG", -3: "IPGC_EBADCSR
 EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_color_graphs_batched", "ipgc_last_error",
            "ipgc_kernel_name", "ipgc_unit_name", "ipgc_version", "ipgc_release_workspaces", "ipgc_server_create",
            "ipgc_server_submit", "ipgc_server_step", "ipgc_server_poll", "ipgc_server_stats_get",
-           "ipgc_server_destroy", "ipgc_push_microbench")
+           "ipgc_server_destroy", "ipgc_push_microbench", "ipgc_bfs")
 FLAG_STEPPED = 1
 FLAG_LIGHT_PULL = 2
 FLAG_LIGHT_PUSH = 4
@@ -136,6 +136,9 @@ def library() -> ctypes.CDLL:
         lib.ipgc_server_stats_get.argtypes = [srv, ctypes.POINTER(ServerStats)]
         lib.ipgc_server_destroy.restype = None
         lib.ipgc_server_destroy.argtypes = [srv]
+        lib.ipgc_bfs.restype = i32
+        lib.ipgc_bfs.argtypes = [vp, vp, i64, i64, i64, i32, ctypes.POINTER(Options), vp, vp,
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Trace)]
         lib.ipgc_push_microbench.restype = i32
         lib.ipgc_push_microbench.argtypes = [i64, i32, i32, i32, vp, vp, i64, ctypes.POINTER(ctypes.c_int64),
                                              ctypes.POINTER(ctypes.c_int64)]
@@ -348,6 +351,43 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
             ctypes.c_void_p(out.data_ptr() if N else 0), rounds.ctypes.data_as(ctypes.c_void_p), call.trace_ref())
     _check(rc)
     return call.finish(BatchColoring(out, rounds[:G].tolist(), node_off))
+
+
+@dataclass
+class BfsResult:
+    dist: "object"      # torch.int32 tensor on the device: hops from the source, -1 if unreachable
+    levels: int         # non-empty frontiers
+    frontier_sizes: list | None = None
+    topology: list | None = None
+
+
+def bfs(rowptr, colidx, source: int, mode="hybrid", *, threshold: int = 0, workgroups: int = 0,
+        validate: int = VALIDATE_DEFAULT, out=None, stream=None, trace: bool = False) -> BfsResult:
+    """Breadth-first search from `source` on the device CSR under the keep-the-worklist hybrid
+    schedule (``ipgc_bfs``)."""
+    import torch
+
+    if rowptr.dtype != torch.int32 or colidx.dtype != torch.int32:
+        raise TypeError("rowptr and colidx must be int32")
+    n, m = rowptr.numel() - 1, colidx.numel()
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=rowptr.device)
+    call = _Call(threshold, 0, 0, validate, False, trace, max(n, 1), 0, 0, workgroups)
+    levels = ctypes.c_int32(-1)
+    if stream is None:
+        stream = torch.cuda.current_stream(rowptr.device)
+    with torch.cuda.device(rowptr.device):
+        rc = library().ipgc_bfs(ctypes.c_void_p(rowptr.data_ptr()), ctypes.c_void_p(colidx.data_ptr() if m else 0),
+                                n, m, int(source), _mode(mode), ctypes.byref(call.opts),
+                                ctypes.c_void_p(stream.cuda_stream), ctypes.c_void_p(out.data_ptr() if n else 0),
+                                ctypes.byref(levels), call.trace_ref())
+    _check(rc)
+    res = BfsResult(out, levels.value)
+    if call.tr is not None:
+        k = call.tr.recorded
+        res.frontier_sizes = list(call._wl[:k])
+        res.topology = list(call._topo[:k])
+    return res
 
 
 def push_microbench(n: int, count: int = 1000, nowl: bool = False, atomic: bool = False):

@@ -6,7 +6,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ipgc.hip", "ipgc_server.hip", "ipgc_micro.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("ipgc.hip", "ipgc_server.hip", "ipgc_micro.hip", "ipgc_bfs.hip")]
 LIB = os.path.join(HERE, "libipgc.so")
 ARCH = "gfx950"
 

@@ -532,6 +532,7 @@ void ipgc_release_workspaces(void) {
     }
     (void)hipSetDevice(cur);
     ipgc::g_ws.clear();
+    ipgc::release_bfs_workspaces();
 }
 
 }  // extern "C"

@@ -80,4 +80,7 @@ struct Params {
 // Validates options (NULL: defaults) and mode into p; clears the out fields of a profile.
 int parse_options(const ipgc_options *opt, int mode, Params *p);
 
+// Frees the cached buffers of the BFS entry point on every device.
+void release_bfs_workspaces();
+
 }  // namespace ipgc
