@@ -97,6 +97,8 @@ def parse():
     p.add_argument("--batch-graphs", type=int, default=4096, help="--config 4: number of graphs")
     p.add_argument("--mode", default=None, choices=["hybrid", "data", "topology", "rebuild"],
                    help="round schedule (default: the tuned one for the workload's class, else hybrid)")
+    p.add_argument("--tail-workgroups", type=int, default=None,
+                   help="workgroups kept for the small rounds at the end (0: default, -1: all; overrides tuning)")
     p.add_argument("--light", default=None, choices=["auto", "pull", "push"],
                    help="how light nodes learn their neighbours' colors (default: tuned, else auto)")
     p.add_argument("--tune-table", default=None, help="JSON table of tuned options (default: the package's)")
@@ -500,6 +502,8 @@ def main():
         tuned["schedule"] = args.mode
     if args.light:
         tuned["light"] = args.light
+    if args.tail_workgroups is not None:
+        tuned["tail_workgroups"] = args.tail_workgroups
     kw = at.call_kwargs(tuned, w.n)
     mode = kw["mode"]
     log("options (%s, class %s): %s" % ("tuned" if choice else "defaults", at.class_key(feats), kw))

@@ -115,7 +115,10 @@ typedef struct ipgc_options {
     ipgc_profile *profile;     /* optional per-kernel timing and work counts (NULL: none) */
     int32_t workgroups;        /* workgroups of the round kernels (0: one per 4096 nodes, at most what
                                   the device keeps resident at once; larger values are clamped to that) */
-    int32_t reserved;          /* must be 0 */
+    int32_t tail_workgroups;   /* once a data-driven round has at most 32 * tail_workgroups active nodes,
+                                  only this many workgroups stay in the cooperative round loop (cheaper
+                                  grid barriers for the long tail of small rounds; 0: default, negative:
+                                  all workgroups stay) */
 } ipgc_options;
 
 /* Option flags. */

@@ -75,7 +75,7 @@ class Options(ctypes.Structure):
     _fields_ = [("threshold", ctypes.c_int64), ("light_max_degree", ctypes.c_int32),
                 ("hub_min_degree", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("profile", ctypes.POINTER(Profile)), ("workgroups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("tail_workgroups", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -188,7 +188,7 @@ class _Call:
     """Marshalled options, optional profile and optional trace of one library call."""
 
     def __init__(self, threshold, light_max_degree, hub_min_degree, validate, stepped, trace, trace_cap,
-                 profile_mask, timeline, workgroups=0, light="auto", racy=False):
+                 profile_mask, timeline, workgroups=0, light="auto", racy=False, tail_workgroups=0):
         self.prof = None
         if profile_mask or timeline:
             self.prof = Profile(int(profile_mask))
@@ -198,7 +198,8 @@ class _Call:
                 self.prof.phase_capacity = int(timeline)
         self.opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), int(validate),
                             (FLAG_STEPPED if stepped else 0) | LIGHT[light] | (FLAG_RACY if racy else 0),
-                            ctypes.pointer(self.prof) if self.prof is not None else None, int(workgroups), 0)
+                            ctypes.pointer(self.prof) if self.prof is not None else None, int(workgroups),
+                            int(tail_workgroups))
         self.tr = None
         if trace:
             cap = max(1, min(int(trace_cap), TRACE_CAPACITY))
@@ -226,7 +227,8 @@ class _Call:
 def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_degree: int = 0,
                 hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT, stepped: bool = False, out=None,
                 stream=None, trace: bool = False, profile_mask: int = 0, timeline: int = 0,
-                workgroups: int = 0, light: str = "auto", racy: bool = False) -> Coloring:
+                workgroups: int = 0, light: str = "auto", racy: bool = False,
+                tail_workgroups: int = 0) -> Coloring:
     """Color the symmetric CSR graph (``rowptr``: int32[n+1], ``colidx``: int32[m], both on the
     HIP device) and return the 1-based colors and round count.  ``mode`` is "topology", "data"
     or "hybrid"; ``threshold`` is H for hybrid rounds (0: floor(6n/10)).  ``stepped`` runs one
@@ -234,9 +236,11 @@ def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_
     never the result.  ``trace`` returns the per-round worklist sizes and degree sums;
     ``profile_mask`` times the selected kernel kinds with HIP events (bit k = kind k); ``timeline``
     > 0 records that many device wall-clock ticks at the round-step boundaries; ``workgroups`` sets
-    the round kernels' workgroup count (0: automatic); ``light`` is "pull", "push" or "auto" (how
-    nodes of degree <= light_max_degree learn their neighbours' colors); ``racy`` selects the
-    in-place mode (a proper coloring that depends on timing, not the synchronous one)."""
+    the round kernels' workgroup count (0: automatic) and ``tail_workgroups`` how many of them stay
+    for the small data-driven rounds at the end (0: default, negative: all); ``light`` is "pull",
+    "push" or "auto" (how nodes of degree <= light_max_degree learn their neighbours' colors);
+    ``racy`` selects the in-place mode (a proper coloring that depends on timing, not the
+    synchronous one)."""
     import torch
 
     if rowptr.dtype != torch.int32 or colidx.dtype != torch.int32:
@@ -254,7 +258,7 @@ def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_
     elif out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() or out.device != rowptr.device:
         raise ValueError("out must be a contiguous int32 tensor of n entries on the graph's device")
     call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, n, profile_mask, timeline,
-                 workgroups, light, racy)
+                 workgroups, light, racy, tail_workgroups)
     rounds = ctypes.c_int32(-1)
     if stream is None:
         stream = torch.cuda.current_stream(rowptr.device)
@@ -311,7 +315,7 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
                          light_max_degree: int = 0, hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT,
                          stepped: bool = False, out=None, stream=None, trace: bool = False,
                          profile_mask: int = 0, workgroups: int = 0, light: str = "auto",
-                         racy: bool = False) -> BatchColoring:
+                         racy: bool = False, tail_workgroups: int = 0) -> BatchColoring:
     """Color many graphs in one launch.  ``rowptr_packed`` (int32[N+G]) and ``colidx_packed``
     (int32[M]) are device tensors in the layout of ``pack_graphs``; ``node_off`` and ``edge_off``
     (G+1 int64 each) are host arrays.  Each graph gets the coloring and round count it gets alone.
@@ -339,7 +343,7 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
     elif out.dtype != torch.int32 or out.numel() != N or not out.is_contiguous() or out.device != dev:
         raise ValueError("out must be a contiguous int32 tensor of N entries on the batch's device")
     call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, N, profile_mask, 0, workgroups,
-                 light, racy)
+                 light, racy, tail_workgroups)
     rounds = np.full(max(G, 1), -1, dtype=np.int32)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
@@ -434,9 +438,9 @@ class Server:
 
     def __init__(self, node_capacity: int, edge_capacity: int, max_jobs: int = 4096, rounds_per_step: int = 0,
                  mode="hybrid", threshold: int = 0, light_max_degree: int = 0, hub_min_degree: int = 0,
-                 workgroups: int = 0, light: str = "auto", racy: bool = False):
+                 workgroups: int = 0, light: str = "auto", racy: bool = False, tail_workgroups: int = 0):
         opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), VALIDATE_DEFAULT,
-                       LIGHT[light] | (FLAG_RACY if racy else 0), None, int(workgroups), 0)
+                       LIGHT[light] | (FLAG_RACY if racy else 0), None, int(workgroups), int(tail_workgroups))
         cfg = ServerConfig(int(node_capacity), int(edge_capacity), int(max_jobs), int(rounds_per_step), _mode(mode),
                            0, opts)
         self._h = ctypes.c_void_p()

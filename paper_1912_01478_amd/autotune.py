@@ -25,8 +25,10 @@ KNOBS = {
     "hub_min_degree": [0, 256, 4096, 16384],
     "schedule": ["hybrid", "data", "hybrid_h2", "hybrid_h10", "topology", "rebuild"],
     "light": ["auto", "pull", "push"],
+    "tail_workgroups": [0, -1, 32, 64, 128],
 }
-DEFAULT = {"workgroups": 0, "light_max_degree": 0, "hub_min_degree": 0, "schedule": "hybrid", "light": "auto"}
+DEFAULT = {"workgroups": 0, "light_max_degree": 0, "hub_min_degree": 0, "schedule": "hybrid", "light": "auto",
+           "tail_workgroups": 0}
 TABLE_VERSION = 1
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_options.json")
 
@@ -45,7 +47,7 @@ def schedule_args(schedule: str, n: int) -> dict:
 def call_kwargs(choice: dict, n: int) -> dict:
     """Keyword arguments of color_graph / color_graphs_batched for a tuned choice."""
     kw = schedule_args(choice.get("schedule", "hybrid"), n)
-    for k in ("workgroups", "light_max_degree", "hub_min_degree"):
+    for k in ("workgroups", "light_max_degree", "hub_min_degree", "tail_workgroups"):
         kw[k] = int(choice.get(k, 0))
     kw["light"] = choice.get("light", "auto")
     lm = kw["light_max_degree"] or 32

@@ -201,8 +201,8 @@ int parse_options(const ipgc_options *opt, int mode, Params *p) {
     p->racy = (o.flags & IPGC_FLAG_RACY) != 0;
     if (p->racy && p->light < 0) p->light = 1;
     if (o.workgroups < 0) return fail(IPGC_EINVAL, "negative workgroups %d", o.workgroups);
-    if (o.reserved != 0) return fail(IPGC_EINVAL, "reserved option field must be 0");
     p->workgroups = o.workgroups;
+    p->tail_groups = o.tail_workgroups == 0 ? kDefaultTailGroups : std::max(0, o.tail_workgroups);
     p->check_ids = o.validate != IPGC_VALIDATE_NONE;
     p->stepped = (o.flags & IPGC_FLAG_STEPPED) != 0;
     p->threshold = o.threshold;
@@ -308,6 +308,7 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
     if (P.light == 0 || (P.light < 0 && n_wide > 0)) d.light_pull = kPushAll;
     else d.light_pull = n_wide > 0 ? kPullLight : kPullOnly;
     d.racy = P.racy ? 1 : 0;
+    d.tail_groups = P.tail_groups;
     d.discard = P.mode == IPGC_MODE_REBUILD ? 1 : 0;
     if (P.check_ids && n_light > 0) {
         TRY(pf.begin(kKindCheck));

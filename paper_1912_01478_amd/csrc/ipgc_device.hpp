@@ -114,6 +114,7 @@ struct Barrier {
     Line gen;             // global generation
     Line xgen[kMaxXcc];   // generation released per XCD
     Line setup;           // one-time flat barrier counter
+    unsigned xcc_of[kMaxRoundBlocks];  // XCD of every workgroup (for a smaller set of participants)
 };
 
 // Scalars shared by every kernel of a call.
@@ -188,6 +189,7 @@ struct DevT {
     int32_t light_pull;      // kPushAll, kPullLight or kPullOnly: how class L learns its neighbours' colors
     int32_t racy;            // in-place mode: losers uncolor at once, L assigns avoid in-flight tentatives
     int32_t discard;         // topology-driven rounds keep no worklist; it is rebuilt when data rounds start
+    int32_t tail_groups;     // workgroups that stay in the round loop for small data-driven rounds (0: all)
 
     // global id of a neighbour stored in row entry k of node v
     __device__ __forceinline__ int32_t base(int32_t v) const { return gbase ? gbase[v] : 0; }
@@ -247,6 +249,7 @@ __device__ __forceinline__ unsigned xcc_id() {
 struct GridBarrier {
     Barrier *b;
     unsigned xcc, nxcc, gen;
+    unsigned xs;  // participating workgroups on this workgroup's XCD
 
     // One-time setup: count the workgroups of every XCD (flat barrier with a
     // per-workgroup release and acquire; used once per launch).
@@ -255,6 +258,7 @@ struct GridBarrier {
         xcc = xcc_id();
         if (threadIdx.x == 0) {
             add_agent(&b->xsize[xcc].v, 1u);
+            b->xcc_of[blockIdx.x] = xcc;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             add_agent(&b->setup.v, 1u);
             while (ld_agent(&b->setup.v) < gridDim.x) __builtin_amdgcn_s_sleep(2);
@@ -263,7 +267,22 @@ struct GridBarrier {
         __syncthreads();
         nxcc = 0;
         for (int i = 0; i < kMaxXcc; ++i) nxcc += ld_agent(&b->xsize[i].v) > 0;
+        xs = ld_agent(&b->xsize[xcc].v);
         gen = 0;
+    }
+
+    // From now on only workgroups 0 .. g-1 take part (every one of them calls
+    // this at the same point, between two barriers; the others have left).
+    __device__ void shrink(int g) {
+        __shared__ unsigned s_x[kMaxXcc];
+        if (threadIdx.x < kMaxXcc) s_x[threadIdx.x] = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < g; i += blockDim.x) atomicAdd(&s_x[b->xcc_of[i] & (kMaxXcc - 1)], 1u);
+        __syncthreads();
+        xs = s_x[xcc];
+        nxcc = 0;
+        for (int i = 0; i < kMaxXcc; ++i) nxcc += s_x[i] > 0;
+        __syncthreads();
     }
 
     __device__ void sync() {
@@ -271,7 +290,6 @@ struct GridBarrier {
         __syncthreads();
         if (threadIdx.x == 0) {
             const unsigned g = gen;
-            const unsigned xs = ld_agent(&b->xsize[xcc].v);
             if (add_agent(&b->xcnt[xcc].v, 1u) == xs - 1) {
                 st_agent(&b->xcnt[xcc].v, 0u);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // write back this XCD's L2
@@ -320,6 +338,42 @@ __device__ __forceinline__ int block_scan(int x, int *total) {
     *total = s_wave[31];
     __syncthreads();
     return excl;
+}
+
+// Three block-wide exclusive scans at once (one int per thread each), with
+// the barriers of one.
+__device__ __forceinline__ void block_scan3(const int (&x)[3], int (&ex)[3], int (&total)[3]) {
+    __shared__ int s_wave[3][32];
+    const int lane = lane_id(), w = threadIdx.x / kWave, nw = (blockDim.x + kWave - 1) / kWave;
+    int incl[3] = {x[0], x[1], x[2]};
+    for (int o = 1; o < kWave; o <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int y = __shfl_up(incl[k], o);
+            if (lane >= o) incl[k] += y;
+        }
+    }
+    if (lane == kWave - 1) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s_wave[k][w] = incl[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        int acc = 0;
+        for (int i = 0; i < nw; ++i) {
+            const int t = s_wave[threadIdx.x][i];
+            s_wave[threadIdx.x][i] = acc;
+            acc += t;
+        }
+        s_wave[threadIdx.x][31] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        ex[k] = s_wave[k][w] + incl[k] - x[k];
+        total[k] = s_wave[k][31];
+    }
+    __syncthreads();
 }
 
 // Ordered append of the flagged threads of the workgroup: returns each flagged
@@ -597,15 +651,18 @@ struct RoundIn {
 
 // Load the segment counts of list `src` and build the prefix sums in shared
 // memory (all threads of the workgroup call this).
+// Segments past the first `writers` (workgroups that had left the round loop
+// when the list was written) count as empty.
 template <class D>
-__device__ void load_segments(const D &d, int src, int32_t (*pre)[kMaxRoundBlocks + 1]) {
+__device__ void load_segments(const D &d, int src, int32_t (*pre)[kMaxRoundBlocks + 1], int writers) {
+    static_assert(kNumClasses == 3, "one fused scan covers the three classes");
     const int nb = gridDim.x;
+    int x[kNumClasses], ex[kNumClasses], tot[kNumClasses];
+    for (int k = 0; k < kNumClasses; ++k) x[k] = threadIdx.x < (unsigned)writers ? d.seg_cnt[src][k * nb + threadIdx.x] : 0;
+    block_scan3(x, ex, tot);
     for (int k = 0; k < kNumClasses; ++k) {
-        const int32_t x = threadIdx.x < (unsigned)nb ? d.seg_cnt[src][k * nb + threadIdx.x] : 0;
-        int tot;
-        const int ex = block_scan(x, &tot);
-        if (threadIdx.x < (unsigned)nb) pre[k][threadIdx.x] = ex;
-        if (threadIdx.x == 0) pre[k][nb] = tot;
+        if (threadIdx.x < (unsigned)nb) pre[k][threadIdx.x] = ex[k];
+        if (threadIdx.x == 0) pre[k][nb] = tot[k];
     }
     __syncthreads();
 }
@@ -639,23 +696,37 @@ __device__ RoundIn round_view(const D &d, int r, int32_t (*pre)[kMaxRoundBlocks 
     return in;
 }
 
+// This workgroup's work-counter totals (shared memory, one set per kernel).
+__device__ __forceinline__ unsigned long long *unit_totals() {
+    __shared__ unsigned long long s_u[kNumUnits];
+    return s_u;
+}
+
+// Work counters: 32 bits per thread within a step (a thread counts far fewer
+// than 2^32 units in one step of any graph that fits in memory), folded into
+// the workgroup's 64-bit shared totals at the end of each step, written to
+// d.units[i][block] at the end of the kernel.
 struct Units {
-    int64_t u[kNumUnits];
+    uint32_t u[kNumUnits];
     __device__ Units() {
         for (int i = 0; i < kNumUnits; ++i) u[i] = 0;
+        if (threadIdx.x < kNumUnits) unit_totals()[threadIdx.x] = 0;
+        __syncthreads();
     }
-    // per-workgroup totals into d.units[i][block]
+    // every thread of the workgroup calls this at the same point
+    __device__ void fold() {
+        unsigned long long *tot = unit_totals();
+        for (int i = 0; i < kNumUnits; ++i) {
+            const int64_t s = wave_sum((int64_t)u[i]);
+            if (lane_id() == 0 && s) atomicAdd(&tot[i], (unsigned long long)s);
+            u[i] = 0;
+        }
+    }
     template <class D>
     __device__ void flush(const D &d) {
-        __shared__ unsigned long long s_u[kNumUnits];
-        if (threadIdx.x < kNumUnits) s_u[threadIdx.x] = 0;
+        fold();
         __syncthreads();
-        for (int i = 0; i < kNumUnits; ++i) {
-            const int64_t s = wave_sum(u[i]);
-            if (lane_id() == 0 && s) atomicAdd(&s_u[i], (unsigned long long)s);
-        }
-        __syncthreads();
-        if (threadIdx.x < kNumUnits) d.units[threadIdx.x * gridDim.x + blockIdx.x] += (int64_t)s_u[threadIdx.x];
+        if (threadIdx.x < kNumUnits) d.units[threadIdx.x * gridDim.x + blockIdx.x] += (int64_t)unit_totals()[threadIdx.x];
         __syncthreads();
     }
 };
@@ -697,8 +768,8 @@ __device__ __forceinline__ int32_t first_free_word(const uint8_t *F, MapRef fm, 
 }
 
 template <class D>
-__device__ void assign_step(const D &d, const RoundIn &in, Units &un) {
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+__device__ void assign_step(const D &d, const RoundIn &in, Units &un, int G) {
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)G * blockDim.x;
     const int64_t gw = gt / kWave, nw = nt / kWave;
     const int lane = lane_id();
     // class L: a thread per node; first free byte of the byte map (a 4-byte word at a time), or
@@ -752,6 +823,7 @@ __device__ void assign_step(const D &d, const RoundIn &in, Units &un) {
             un.u[kUAssignNodes] += 1;
         }
     }
+    un.fold();
 }
 
 // ============================================================== step 2: conflicts, commit, push
@@ -762,31 +834,42 @@ __device__ void assign_step(const D &d, const RoundIn &in, Units &un) {
 // push step; losers go to the workgroup's segment of the out list.
 
 // Write color t into the byte maps of the neighbours in row entries [b, e)
-// (neighbour ids offset by `base`, their maps by `fsh`), one wavefront, four
-// independent loads in flight per lane.
+// (neighbour ids offset by `base`, their maps by `fsh`), `width` threads with
+// ranks `rank` (a wavefront or a team of them), four independent loads in
+// flight per thread.  A committed neighbour never reads its map again and is
+// skipped; so are class L neighbours when they read colors themselves.  A
+// neighbour that commits in the same step may still be written: harmless.
 template <class D>
-__device__ __forceinline__ void push_row_wave(const D &d, int64_t b, int64_t e, int32_t t, int32_t base,
-                                              int64_t fsh) {
-    const int lane = lane_id();
-    for (int64_t k0 = b; k0 < e; k0 += 4 * kWave) {
+__device__ __forceinline__ void push_row(const D &d, int64_t b, int64_t e, int32_t t, int32_t base, int64_t fsh,
+                                         int rank, int width) {
+    for (int64_t k0 = b; k0 < e; k0 += 4 * width) {
         int32_t w[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int64_t k = k0 + j * kWave + lane;
+            const int64_t k = k0 + j * width + rank;
             w[j] = k < e ? d.colidx[k] + base : -1;
         }
-        if (d.light_pull == kPullLight) {  // L neighbours read colors themselves
+        bool skip[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (w[j] >= 0 && d.cls[w[j]] == kL) w[j] = -1;
+        for (int j = 0; j < 4; ++j) {
+            // both loads are issued before either is tested
+            const int32_t cw = w[j] >= 0 ? d.c[w[j]] : 1;
+            const int8_t kw = w[j] >= 0 && d.light_pull == kPullLight ? d.cls[w[j]] : (int8_t)kW;
+            skip[j] = cw > 0 || kw == kL;
         }
         MapRef fm[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? map_of(d, w[j], fsh) : MapRef{0, 0};
+        for (int j = 0; j < 4; ++j) fm[j] = skip[j] ? MapRef{0, 0} : map_of(d, w[j], fsh);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             if ((uint32_t)t <= fm[j].size) d.F[fm[j].pos + t - 1] = 1;
     }
+}
+
+template <class D>
+__device__ __forceinline__ void push_row_wave(const D &d, int64_t b, int64_t e, int32_t t, int32_t base,
+                                              int64_t fsh) {
+    push_row(d, b, e, t, base, fsh, lane_id(), kWave);
 }
 
 // Ring scan of W/M node v by one wavefront: looks for a smaller neighbour with
@@ -851,9 +934,123 @@ __device__ bool ring_scan_wave(const D &d, int32_t v, int32_t t, int wide, Units
     return lose;
 }
 
+// Conflict test of the W/M nodes by teams of T wavefronts (T = 2, 4, 8 or 16)
+// for rounds with few of them, so a long ring is read up to T times faster
+// than by one wavefront: a pass reads 4 * T * 64 entries.  The teams of a
+// workgroup run their passes together (the pass loop ends when none of them
+// has entries left), so its workgroup barriers are uniform.  Kept entries
+// are placed through a shared counter per team, so their order in the ring
+// varies; the set, and with it every outcome, does not.
 template <class D>
-__device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, int32_t r, Units &un) {
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+__device__ void conflict_wide_teams(const D &d, const RoundIn &in, const OutSegs &os, int32_t r, Units &un, int G, int T,
+                                    bool discard, const int32_t (&seg_base)[kNumClasses], int *s_cnt,
+                                    unsigned long long *s_deg) {
+    constexpr int kPass = 4;
+    __shared__ int32_t s_kept[kRoundWaves], s_hit[kRoundWaves];
+    const int span = T * kWave, tpb = kRoundWaves / T;
+    const int tm = threadIdx.x / span, tl = threadIdx.x % span, lane = lane_id();
+    const int64_t nteams = (int64_t)G * tpb;
+    const int32_t nW = in.cv[kW].total, nWM = nW + in.cv[kM].total;
+    // the slot loop depends on the workgroup only
+    for (int64_t i0 = (int64_t)blockIdx.x * tpb; i0 < nWM; i0 += nteams) {
+        const int64_t i = i0 + tm;
+        const bool hub = i >= nW;
+        int32_t v = 0, t = 0, start = 0, len = 0, cap = 0;
+        int64_t b = 0, e = 0;
+        bool act = i < nWM;
+        if (act) {
+            v = hub ? in.cv[kM].at((int32_t)(i - nW)) : in.cv[kW].at((int32_t)i);
+            const int32_t cv = d.c[v];
+            act = !(in.topo && cv > 0);
+            t = -cv;
+            b = d.rowptr[v];
+            e = d.rowptr[v + 1];
+            cap = (int32_t)(e - b);
+            start = d.lstart[v];
+            len = d.llen[v];
+        }
+        if (tl == 0) {
+            s_kept[tm] = 0;
+            s_hit[tm] = 0;
+        }
+        __syncthreads();
+        int32_t read = 0;  // the same in every thread of a team
+        bool scanning = act && len > 0;
+        while (__syncthreads_or(scanning)) {
+            int32_t u[kPass], cu[kPass];
+#pragma unroll
+            for (int j = 0; j < kPass; ++j) {
+                const int32_t k = read + j * span + tl;
+                u[j] = -1;
+                if (scanning && k < len) {
+                    int32_t p = start + k;
+                    if (p >= cap) p -= cap;
+                    u[j] = d.lower[b + p];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kPass; ++j) cu[j] = u[j] >= 0 ? d.c[u[j]] : 0;
+            bool hit = false;
+#pragma unroll
+            for (int j = 0; j < kPass; ++j) hit |= u[j] >= 0 && iabs(cu[j]) == t;
+            __syncthreads();  // every read of the pass is done before kept entries reuse ring slots
+#pragma unroll
+            for (int j = 0; j < kPass; ++j) {
+                const bool keep = u[j] >= 0 && cu[j] <= 0;
+                const uint64_t km = __ballot(keep);
+                int wb = 0;
+                if (lane == 0 && km) wb = atomicAdd(&s_kept[tm], (int)__popcll(km));
+                wb = __shfl(wb, 0);
+                if (keep) {
+                    int32_t p = start + len + wb + (int32_t)__popcll(km & lanes_below());
+                    while (p >= cap) p -= cap;
+                    d.lower[b + p] = u[j];
+                }
+            }
+            if (hit) s_hit[tm] = 1;
+            __syncthreads();
+            if (scanning) {
+                read += min(kPass * span, len - read);
+                scanning = read < len && s_hit[tm] == 0;
+            }
+        }
+        const bool lose = act && s_hit[tm] != 0;
+        if (act && tl == 0) {
+            const int32_t kept = s_kept[tm];
+            un.u[kUConflictNodes] += 1;
+            un.u[kUConflictEntries] += read;
+            un.u[kUListWrites] += kept;
+            if (len > 0) {
+                int32_t s2 = start + read;
+                while (s2 >= cap) s2 -= cap;
+                d.lstart[v] = s2;
+                d.llen[v] = len - read + kept;
+            }
+            const int q = hub ? kM : kW;
+            if (lose) {
+                if (d.racy) d.c[v] = 0;
+                const int p = atomicAdd(&s_cnt[q], 1);
+                atomicAdd(&s_deg[q], (unsigned long long)(e - b));
+                if (!discard) os.list[seg_base[q] + p] = v;
+            } else {
+                d.c[v] = t;
+                un.u[kUCommits] += 1;
+                if (d.grounds) atomicMax(&d.grounds[d.gidx[v]], r);
+                if (d.gleft) atomicSub(&d.gleft[d.gidx[v]], 1);
+                if (hub) d.hub_won[atomicAdd(&d.ct->hub_winners, 1)] = HubRec{b, e, d.fshift(v), t, d.base(v)};
+            }
+        }
+        if (act && !lose && !hub) {
+            push_row(d, b, e, t, d.base(v), d.fshift(v), tl, span);
+            if (tl == 0) un.u[kUPushEntries] += e - b;
+        }
+        __syncthreads();  // the team counters are reset for the next slot
+    }
+}
+
+template <class D>
+__device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, int32_t r, Units &un, int G) {
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)G * blockDim.x;
     const int64_t gw = gt / kWave, nw = nt / kWave;
     const int lane = lane_id();
     __shared__ int s_cnt[kNumClasses];
@@ -871,7 +1068,10 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
     // classes W and M: a wavefront per node.  W winners write their color into
     // their neighbours' byte maps at once; M winners are recorded for the push step.
     const int32_t nW = in.cv[kW].total, nWM = nW + in.cv[kM].total;
-    for (int64_t i = gw; i < nWM; i += nw) {
+    int T = 1;  // wavefronts per W/M node: more when there are few of them
+    while (T < kRoundWaves && (int64_t)nWM * T * 2 <= nw) T *= 2;
+    if (T > 1) conflict_wide_teams(d, in, os, r, un, G, T, discard, seg_base, s_cnt, s_deg);
+    for (int64_t i = gw; i < nWM && T == 1; i += nw) {
         const bool hub = i >= nW;
         const int32_t v = hub ? in.cv[kM].at((int32_t)(i - nW)) : in.cv[kW].at((int32_t)i);
         const int32_t cv = d.c[v];
@@ -946,14 +1146,16 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
                 int32_t w[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) w[j] = k0 + j < e ? d.colidx[k0 + j] + gb : -1;
-                if (d.light_pull == kPullLight) {
+                bool skip[4];  // committed neighbours, and class L ones when they pull
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (w[j] >= 0 && d.cls[w[j]] == kL) w[j] = -1;
+                for (int j = 0; j < 4; ++j) {
+                    const int32_t cw = w[j] >= 0 ? d.c[w[j]] : 1;
+                    const int8_t kw = w[j] >= 0 && d.light_pull == kPullLight ? d.cls[w[j]] : (int8_t)kW;
+                    skip[j] = cw > 0 || kw == kL;
                 }
                 MapRef fm[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) fm[j] = w[j] >= 0 ? map_of(d, w[j], fsh) : MapRef{0, 0};
+                for (int j = 0; j < 4; ++j) fm[j] = skip[j] ? MapRef{0, 0} : map_of(d, w[j], fsh);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     if ((uint32_t)t <= fm[j].size) d.F[fm[j].pos + t - 1] = 1;
@@ -985,6 +1187,7 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
         os.cnt[threadIdx.x * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
         os.deg[threadIdx.x * gridDim.x + blockIdx.x] = (int64_t)s_deg[threadIdx.x];
     }
+    un.fold();
 }
 
 // Push step: the rows of this round's committed hubs, spread over every
@@ -992,12 +1195,12 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
 // kRoundBlock hubs at a time (row bounds, color, chunk prefix sums) in shared
 // memory; wavefront w then takes chunks w, w + nw, ... of the staged batch.
 template <class D>
-__device__ void hub_push_step(const D &d, int32_t nwon, Units &un) {
+__device__ void hub_push_step(const D &d, int32_t nwon, Units &un, int G) {
     constexpr int kChunk = 4 * kWave;
     __shared__ int64_t s_b[kRoundBlock], s_e[kRoundBlock], s_fsh[kRoundBlock];
     __shared__ int32_t s_t[kRoundBlock], s_base[kRoundBlock], s_pre[kRoundBlock + 1];
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int64_t nw = (int64_t)G * blockDim.x / kWave;
     for (int32_t h0 = 0; h0 < nwon; h0 += blockDim.x) {
         const int32_t h = h0 + threadIdx.x;
         int32_t chunks = 0;
@@ -1029,6 +1232,7 @@ __device__ void hub_push_step(const D &d, int32_t nwon, Units &un) {
         }
         __syncthreads();
     }
+    un.fold();
 }
 
 // ============================================================== round kernels
@@ -1036,7 +1240,7 @@ __device__ void hub_push_step(const D &d, int32_t nwon, Units &un) {
 // Round bookkeeping by workgroup 0 (all its threads): trace, work units, and
 // the stop test (a round that starts with an empty worklist is not run).
 template <class D>
-__device__ void round_record(const D &d, int r, const RoundIn &in, bool reset_hubs) {
+__device__ void round_record(const D &d, int r, const RoundIn &in, bool reset_hubs, int writers) {
     __shared__ unsigned long long s_deg[kNumClasses];
     if (in.total == 0) {
         if (threadIdx.x == 0) {
@@ -1049,7 +1253,7 @@ __device__ void round_record(const D &d, int r, const RoundIn &in, bool reset_hu
     __syncthreads();
     if (r > 1) {
         for (int k = 0; k < kNumClasses; ++k) {
-            const int64_t x = threadIdx.x < gridDim.x ? d.seg_deg[r & 1][k * gridDim.x + threadIdx.x] : 0;
+            const int64_t x = threadIdx.x < (unsigned)writers ? d.seg_deg[r & 1][k * gridDim.x + threadIdx.x] : 0;
             const int64_t ws = wave_sum(x);
             if (lane_id() == 0 && ws) atomicAdd(&s_deg[k], (unsigned long long)ws);
         }
@@ -1098,10 +1302,10 @@ __device__ __forceinline__ void tick(const D &d, int64_t i) {
 // [b*span_k, (b+1)*span_k) of class k and appends its uncolored nodes, in
 // order, to its own segment.
 template <class D>
-__device__ void rebuild_step(const D &d, int par) {
+__device__ void rebuild_step(const D &d, int par, int G) {
     __shared__ int s_cnt;
     __shared__ unsigned long long s_deg;
-    const int b = blockIdx.x, nb = gridDim.x;
+    const int b = blockIdx.x, nb = G, stride = gridDim.x;
     for (int k = 0; k < kNumClasses; ++k) {
         if (threadIdx.x == 0) {
             s_cnt = 0;
@@ -1111,7 +1315,7 @@ __device__ void rebuild_step(const D &d, int par) {
         const int32_t total = d.ct->class_n[k];
         const int32_t *list = d.static_list + d.ct->static_off[k];
         const int64_t span = ((int64_t)total + nb - 1) / nb, lo = (int64_t)b * span, hi = min<int64_t>(lo + span, total);
-        int32_t *seg = d.seg_list[par] + d.ct->seg_off[k] + (int64_t)b * d.ct->seg_cap[k];
+        int32_t *seg = d.seg_list[par] + d.ct->seg_off[k] + (int64_t)b * d.ct->seg_cap[k];  // segment b of class k
         for (int64_t c0 = lo; c0 < hi; c0 += blockDim.x) {
             const int64_t i = c0 + threadIdx.x;
             const int32_t v = i < hi ? list[i] : 0;
@@ -1123,18 +1327,35 @@ __device__ void rebuild_step(const D &d, int par) {
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            d.seg_cnt[par][k * nb + b] = s_cnt;
-            d.seg_deg[par][k * nb + b] = (int64_t)s_deg;
+            d.seg_cnt[par][k * stride + b] = s_cnt;
+            d.seg_deg[par][k * stride + b] = (int64_t)s_deg;
         }
         __syncthreads();
     }
 }
 
+// Workgroups for a data-driven round with `total` active nodes, given the
+// `G` of the previous round: all of them, until the worklist has at most
+// kTailNodesPerGroup nodes per tail workgroup; then tail_groups of them (at
+// most one node per thread, so no workgroup's out segment can overflow).
+// Fewer participants make each grid barrier cheaper (every workgroup's
+// agent-scope acquire is part of its cost); the worklist only shrinks, so G
+// never grows again.
+constexpr int kTailNodesPerGroup = 32;
+
+template <class D>
+__device__ __forceinline__ int round_groups(const D &d, const RoundIn &in, int G) {
+    if (in.topo || d.tail_groups <= 0 || G <= d.tail_groups) return G;
+    return (int64_t)in.total <= (int64_t)d.tail_groups * kTailNodesPerGroup ? d.tail_groups : G;
+}
+
 // Rounds first .. last (or until the worklist is empty) in one cooperative
 // launch: assign | barrier | conflict | barrier [| hub push | barrier].  Every
 // workgroup reads the same counts after each barrier, so all take the same
-// branches and leave the loop together.  Round 1 reads the static list; a
-// later first round reads the segmented list of its parity.
+// branches and leave the loop together; in the tail of the run, workgroups
+// G and up leave it early (round_groups) and the barrier counts the rest.
+// Round 1 reads the static list; a later first round reads the segmented
+// list of its parity, written by every workgroup.
 template <class D>
 __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int32_t last) {
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
@@ -1142,32 +1363,45 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
     gb.setup(d.bar);
     Units un;
     int32_t r = first;
-    bool discarded = false;  // the previous round kept no worklist
+    int G = gridDim.x;        // workgroups in the round loop
+    int writers = gridDim.x;  // workgroups that wrote the list this round reads
+    bool discarded = false;   // the previous round kept no worklist
     for (; r <= last; ++r) {
-        if (r > 1) load_segments(d, r & 1, pre);
+        if (r > 1) load_segments(d, r & 1, pre, writers);
         RoundIn in = round_view(d, r, pre);
         if (discarded && !in.topo && in.total > 0) {
-            rebuild_step(d, r & 1);
+            rebuild_step(d, r & 1, G);
             gb.sync();
-            load_segments(d, r & 1, pre);
+            writers = G;
+            load_segments(d, r & 1, pre, writers);
             in = round_view(d, r, pre);
         }
         discarded = d.discard && in.topo;
-        if (blockIdx.x == 0) round_record(d, r, in, false);
+        if (blockIdx.x == 0) round_record(d, r, in, false, writers);
         if (in.total == 0) break;
+        const int g2 = round_groups(d, in, G);
+        if (g2 < G) {
+            if ((int)blockIdx.x >= g2) break;
+            gb.shrink(g2);
+            G = g2;
+        }
         tick(d, 3 * (int64_t)(r - 1));
         if (r > 1) {  // round 1's tentative colors (all 1) were set at init
-            assign_step(d, in, un);
+            assign_step(d, in, un, G);
             gb.sync();
         }
         tick(d, 3 * (int64_t)(r - 1) + 1);
-        conflict_step(d, in, out_segs(d, r), r, un);
+        conflict_step(d, in, out_segs(d, r), r, un, G);
+        writers = G;
         gb.sync();
         tick(d, 3 * (int64_t)(r - 1) + 2);
-        // every workgroup reads the count here; it is cleared only after the next barrier
-        const int32_t nwon = (int32_t)ld_agent((unsigned *)&d.ct->hub_winners);
+        // every workgroup reads the count here (one load, shared); it is cleared only after the next barrier
+        __shared__ int32_t s_nwon;
+        if (threadIdx.x == 0) s_nwon = (int32_t)ld_agent((unsigned *)&d.ct->hub_winners);
+        __syncthreads();
+        const int32_t nwon = s_nwon;
         if (nwon > 0) {
-            hub_push_step(d, nwon, un);
+            hub_push_step(d, nwon, un, G);
             gb.sync();
             if (blockIdx.x == 0 && threadIdx.x == 0) d.ct->hub_winners = 0;
         }
@@ -1183,22 +1417,22 @@ template <class D>
 __global__ __launch_bounds__(kRoundBlock) void k_rebuild_round(D d, int32_t r) {
     if (d.ct->finished || r == 1 || !d.ct->prev_discarded) return;
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
-    load_segments(d, r & 1, pre);
+    load_segments(d, r & 1, pre, gridDim.x);
     const RoundIn in = round_view(d, r, pre);
     if (in.topo || in.total == 0) return;
-    rebuild_step(d, r & 1);
+    rebuild_step(d, r & 1, gridDim.x);
 }
 
 template <class D>
 __global__ __launch_bounds__(kRoundBlock) void k_assign_round(D d, int32_t r) {
     if (d.ct->finished) return;
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
-    if (r > 1) load_segments(d, r & 1, pre);
+    if (r > 1) load_segments(d, r & 1, pre, gridDim.x);
     const RoundIn in = round_view(d, r, pre);
-    if (blockIdx.x == 0) round_record(d, r, in, true);
+    if (blockIdx.x == 0) round_record(d, r, in, true, gridDim.x);
     if (in.total == 0 || r == 1) return;  // round 1's tentative colors were set at init
     Units un;
-    assign_step(d, in, un);
+    assign_step(d, in, un, gridDim.x);
     un.flush(d);
 }
 
@@ -1206,11 +1440,11 @@ template <class D>
 __global__ __launch_bounds__(kRoundBlock) void k_conflict_round(D d, int32_t r) {
     if (d.ct->finished) return;
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
-    if (r > 1) load_segments(d, r & 1, pre);
+    if (r > 1) load_segments(d, r & 1, pre, gridDim.x);
     const RoundIn in = round_view(d, r, pre);
     if (in.total == 0) return;
     Units un;
-    conflict_step(d, in, out_segs(d, r), r, un);
+    conflict_step(d, in, out_segs(d, r), r, un, gridDim.x);
     un.flush(d);
 }
 
@@ -1220,7 +1454,7 @@ __global__ __launch_bounds__(kRoundBlock) void k_push_round(D d) {
     const int32_t nwon = d.ct->hub_winners;
     if (nwon == 0) return;
     Units un;
-    hub_push_step(d, nwon, un);
+    hub_push_step(d, nwon, un, gridDim.x);
     un.flush(d);
 }
 

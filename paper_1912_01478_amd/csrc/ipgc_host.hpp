@@ -15,6 +15,7 @@ namespace ipgc {
 
 constexpr int kDefaultLightMax = 32;
 constexpr int kDefaultHubMin = 1024;
+constexpr int kDefaultTailGroups = 32;  // workgroups kept for small data-driven rounds (0: all)
 
 // Message of the last failing call on this thread (ipgc_last_error).
 extern thread_local char g_err[512];
@@ -71,6 +72,7 @@ struct Params {
     bool stepped = false;
     int64_t threshold = 0;  // 0: floor(6n/10) for HYBRID
     int workgroups = 0;     // 0: automatic
+    int tail_groups = 0;    // workgroups kept for small data-driven rounds (0: all)
     int light = -1;         // -1: automatic, 0: push into every byte map, 1: class L pulls
     bool racy = false;      // in-place (timing-dependent) mode
     int mode = IPGC_MODE_HYBRID;

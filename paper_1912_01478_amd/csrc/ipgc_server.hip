@@ -466,6 +466,7 @@ SDev Server::dev_view(int64_t nhigh, int64_t threshold) {
     d.grid = grid;
     d.light_pull = P.light == 1 ? kPullLight : kPushAll;  // jobs of any class may arrive later
     d.racy = P.racy ? 1 : 0;
+    d.tail_groups = P.tail_groups;
     d.discard = P.mode == IPGC_MODE_REBUILD ? 1 : 0;
     return d;
 }

@@ -31,7 +31,7 @@ def test_call_kwargs():
     kw = at.call_kwargs({"schedule": "hybrid_h10", "light_max_degree": 16, "hub_min_degree": 8,
                          "workgroups": 128}, 1000)
     assert kw == {"mode": "hybrid", "threshold": 100, "workgroups": 128, "light_max_degree": 16, "hub_min_degree": 17,
-                  "light": "auto"}
+                  "tail_workgroups": 0, "light": "auto"}
     assert at.call_kwargs(at.DEFAULT, 50)["mode"] == "hybrid"
     assert at.call_kwargs({"schedule": "topology"}, 50)["mode"] == "topology"
     with pytest.raises(ValueError):
@@ -59,7 +59,8 @@ def test_search_finds_the_cheapest_point():
             "light_max_degree": {0: 1, 8: 3, 16: 2},
             "hub_min_degree": {0: 2, 256: 1, 4096: 3, 16384: 4},
             "schedule": {"hybrid": 2, "data": 1, "hybrid_h2": 1.5, "hybrid_h10": 3, "topology": 9, "rebuild": 2.5},
-            "light": {"auto": 1, "pull": 0.5, "push": 2}}
+            "light": {"auto": 1, "pull": 0.5, "push": 2},
+            "tail_workgroups": {0: 1, -1: 2, 32: 0.25, 64: 0.5, 128: 3}}
     inv = {}
 
     def run(stream, **kw):
@@ -72,10 +73,11 @@ def test_search_finds_the_cheapest_point():
                  ("hybrid", 20): "hybrid_h2", ("hybrid", 100): "hybrid_h10"}[(kw["mode"], kw["threshold"])]
         hub = kw["hub_min_degree"] if kw["hub_min_degree"] in cost["hub_min_degree"] else 0
         return 10.0 + cost["workgroups"][kw["workgroups"]] + cost["light_max_degree"][kw["light_max_degree"]] \
-            + cost["hub_min_degree"][hub] + cost["schedule"][sched] + cost["light"][kw["light"]]
+            + cost["hub_min_degree"][hub] + cost["schedule"][sched] + cost["light"][kw["light"]] \
+            + cost["tail_workgroups"][kw["tail_workgroups"]]
 
     best, ms, dms, trials = at.tune(run, 1000, timer=timer)
     assert best == {"workgroups": 128, "light_max_degree": 0, "hub_min_degree": 256, "schedule": "data",
-                    "light": "pull"}
-    assert ms == 14.5 and dms == 21.0
+                    "light": "pull", "tail_workgroups": 32}
+    assert ms == 14.75 and dms == 22.0
     assert len(trials) == len({tuple(sorted(t["choice"].items())) for t in trials})

@@ -119,6 +119,13 @@ def test_batch_options_never_change_the_result(H, light, hub):
     assert_batch_matches_oracle(MEDIUM, "hybrid", threshold=H, light_max_degree=light, hub_min_degree=hub)
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_tail_workgroups(mode):
+    """Small rounds of a batch on fewer workgroups than the first ones: same bits per graph."""
+    assert_batch_matches_oracle(MIXED + MEDIUM[:2], mode, workgroups=256, tail_workgroups=4,
+                                light_max_degree=8, hub_min_degree=200)
+
+
 @pytest.mark.parametrize("light", ["pull", "push"])
 def test_batch_light_modes(light):
     assert_batch_matches_oracle(MIXED + MEDIUM[:2], "hybrid", light=light)

@@ -117,6 +117,15 @@ def test_options_never_change_the_result(H, light, hub):
     assert_parity(g, "hybrid", threshold=H, light_max_degree=light, hub_min_degree=hub)
 
 
+@pytest.mark.parametrize("wg,tail", [(64, 1), (256, 8), (512, 64)])
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("g", SMALL, ids=lambda g: g.name)
+def test_tail_workgroups_same_result(g, mode, wg, tail):
+    """Small data-driven rounds on fewer workgroups (the others leave the cooperative loop and the
+    grid barrier counts the rest): same bits, with every node class in play."""
+    assert_parity(g, mode, workgroups=wg, tail_workgroups=tail, light_max_degree=8, hub_min_degree=200)
+
+
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("g", SMALL, ids=lambda g: g.name)
 def test_stepped_launches_same_result(g, mode):

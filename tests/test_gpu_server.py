@@ -81,6 +81,13 @@ def test_light_pull_server():
         check(drain(srv), ids)
 
 
+def test_tail_workgroups_server():
+    """Steps whose rounds shrink to a few workgroups; the next step starts with all of them."""
+    with _server(workgroups=128, tail_workgroups=2, rounds_per_step=7) as srv:
+        ids = {srv.submit(g.rowptr, g.colidx): g for g in MIX}
+        check(drain(srv), ids)
+
+
 def test_arrivals_while_running():
     """Jobs submitted between steps join the running mix; results are those of each job alone."""
     with _server(rounds_per_step=2) as srv:
