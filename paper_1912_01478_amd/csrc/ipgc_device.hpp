@@ -78,6 +78,7 @@ constexpr int kMaxRoundBlocks = 1024;    // cap on the cooperative grid
 constexpr int kLightMaxLimit = 32;       // thread-per-node pull uses a 64-bit mask: d + 1 <= 64
 constexpr int kMaxXcc = 16;
 constexpr int kWideScanMax = 65536;      // rounds with at most this many active nodes scan rings 4 chunks a pass
+constexpr int kMaskColors = 64;          // colors 1..64 of committed neighbours are bits of a word per node
 
 enum { kL = 0, kW = 1, kM = 2, kNumClasses = 3 };
 
@@ -159,8 +160,9 @@ struct DevT {
     const int64_t *gfshift;  // a server: byte-map shift per graph (null: no shift)
     int32_t *c;              // color state (caller's output)
     const int8_t *cls;       // class per node
-    uint8_t *F;              // byte maps: node v's map is bytes [rowptr[v] + v, rowptr[v + 1] + v], shifted
-                             // by fshift(v)
+    uint64_t *mask;          // per node: bit t - 1 set iff a committed neighbour has color t (t <= 64)
+    uint8_t *F;              // byte maps for colors above 64: node v's map is bytes [rowptr[v] + v,
+                             // rowptr[v + 1] + v] (byte t - 1 for color t), shifted by fshift(v)
     int32_t *lower;          // ring of smaller neighbours per W/M node (region rowptr[v] .. + d)
     int32_t *lstart;         // ring start per node
     int32_t *llen;           // ring length per node
@@ -402,6 +404,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_init(D d, int8_t *cls, int32_t s
         // Round 1 assigns color 1 to every node (no neighbour is committed yet), so the state
         // starts there: tentative color 1, and round 1 skips its assign step.
         d.c[v] = -1;
+        d.mask[v] = 0;
         const int64_t a = d.rowptr[v], e = d.rowptr[v + 1];
         const bool b = a < 0 || e < a || e > d.m || e - a >= INT32_MAX;
         bad |= b;
@@ -745,41 +748,21 @@ struct OutSegs {
 // Every uncolored node takes the smallest color >= 1 that no committed
 // neighbour holds (Section II-C with its footnote on mex; 0 marks uncolored).
 
-// First zero byte of a node's byte map at or after index s (colors are the
-// index + 1).  Reads aligned 4-byte words; bytes before s and past the map end
-// count as taken.  A free byte exists: a node of degree d sees at most d colors.
-__device__ __forceinline__ int32_t first_free_word(const uint8_t *F, MapRef fm, uint32_t s, Units &un) {
-    const uint64_t end = fm.pos + fm.size;
-    uint64_t a = fm.pos + s;
-    for (;;) {
-        const uint64_t wa = a & ~3ull;
-        uint32_t w = *reinterpret_cast<const uint32_t *>(F + wa);
-        un.u[kUMapBytes] += 4;
-        const uint32_t lo = (uint32_t)(a - wa);
-        if (lo) w |= 0xffffffffu >> (32 - 8 * lo);
-        if (end < wa + 4) w |= 0xffffffffu << (8 * (uint32_t)(end - wa));
-        const uint32_t z = (w - 0x01010101u) & ~w & 0x80808080u;
-        // the lowest flagged byte is a zero byte (borrows only flag higher bytes); ffs of its
-        // bit 7 is 8j + 8, so wa + j + 1 - base is the color of byte j
-        if (z) return (int32_t)(wa + (__ffs(z) >> 3) - fm.pos);
-        a = wa + 4;
-        if (a >= end) return (int32_t)fm.size;  // unreachable for a consistent map
-    }
-}
-
 template <class D>
 __device__ void assign_step(const D &d, const RoundIn &in, Units &un, int G) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)G * blockDim.x;
     const int64_t gw = gt / kWave, nw = nt / kWave;
     const int lane = lane_id();
-    // class L: a thread per node; first free byte of the byte map (a 4-byte word at a time), or
-    // first zero bit of a mask of the neighbours' committed colors (four loads in flight)
+    // class L: a thread per node; first zero bit of its color mask (pushed there by committed
+    // neighbours; d <= 32 neighbours leave a zero among the first 33 bits), or of a mask of
+    // its neighbours' committed colors read from their states (four loads in flight)
     for (int64_t i = gt; i < in.cv[kL].total; i += nt) {
         const int32_t v = in.cv[kL].at((int32_t)i);
         const int32_t cv = d.c[v];
         if (in.topo && cv > 0) continue;
         if (d.light_pull == kPushAll) {
-            d.c[v] = -first_free_word(d.F, map_of(d, v, d.fshift(v)), cv < 0 ? (uint32_t)(-cv) - 1u : 0u, un);
+            d.c[v] = -__ffsll((unsigned long long)~d.mask[v]);
+            un.u[kUMapBytes] += 8;
         } else {
             const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
             const int32_t gb = d.base(v);
@@ -799,14 +782,25 @@ __device__ void assign_step(const D &d, const RoundIn &in, Units &un, int G) {
         }
         un.u[kUAssignNodes] += 1;
     }
-    // classes W and M: a wavefront per node, first free byte of the byte map
+    // classes W and M: a wavefront per node, first zero bit of the color mask, else first free
+    // byte of the byte map from color 65 on
     const int32_t nW = in.cv[kW].total, nWM = nW + in.cv[kM].total;
     for (int64_t i = gw; i < nWM; i += nw) {
         const int32_t v = i < nW ? in.cv[kW].at((int32_t)i) : in.cv[kM].at((int32_t)(i - nW));
         const int32_t cv = d.c[v];
         if (in.topo && cv > 0) continue;
+        const uint64_t free = ~d.mask[v];
+        un.u[kUMapBytes] += lane == 0 ? 8 : 0;
+        if (free) {
+            if (lane == 0) {
+                d.c[v] = -__ffsll((unsigned long long)free);
+                un.u[kUAssignNodes] += 1;
+            }
+            continue;
+        }
         const MapRef fm = map_of(d, v, d.fshift(v));
-        uint32_t s = cv < 0 ? (uint32_t)(-cv) - 1u : 0u;  // the previous tentative color, 0-based
+        // from the previous tentative color (0-based; first-fit colors only grow) or color 65
+        uint32_t s = max(cv < 0 ? (uint32_t)(-cv) - 1u : 0u, (uint32_t)kMaskColors);
         int32_t t = (int32_t)fm.size;  // d + 1 is free if nothing smaller is
         for (; s < fm.size; s += kWave) {
             const uint32_t idx = s + lane;
@@ -833,15 +827,35 @@ __device__ void assign_step(const D &d, const RoundIn &in, Units &un, int G) {
 // the byte maps of their neighbours at once, M winners are recorded for the
 // push step; losers go to the workgroup's segment of the out list.
 
-// Write color t into the byte maps of the neighbours in row entries [b, e)
-// (neighbour ids offset by `base`, their maps by `fsh`), `width` threads with
-// ranks `rank` (a wavefront or a team of them), four independent loads in
-// flight per thread.  A committed neighbour never reads its map again and is
-// skipped; so are class L neighbours when they read colors themselves.  A
-// neighbour that commits in the same step may still be written: harmless.
+// Record color t with the neighbours in row entries [b, e) (neighbour ids
+// offset by `base`, their byte maps by `fsh`), `width` threads with ranks
+// `rank` (a wavefront or a team of them), four independent loads in flight per
+// thread.  Colors up to 64 set a bit of the neighbour's mask: a read first,
+// the atomic only if the bit is not set yet (a hub's word takes the same color
+// from many winners).  Larger colors go to byte maps, skipping committed
+// neighbours (which never read their maps again), class L neighbours when they
+// read colors themselves, and maps too short for t.
 template <class D>
 __device__ __forceinline__ void push_row(const D &d, int64_t b, int64_t e, int32_t t, int32_t base, int64_t fsh,
                                          int rank, int width) {
+    if (t <= kMaskColors) {
+        const uint64_t bit = 1ull << (t - 1);
+        for (int64_t k0 = b; k0 < e; k0 += 4 * width) {
+            int32_t w[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t k = k0 + j * width + rank;
+                w[j] = k < e ? d.colidx[k] + base : -1;
+            }
+            uint64_t mw[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) mw[j] = w[j] >= 0 ? d.mask[w[j]] : bit;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (!(mw[j] & bit)) atomicOr((unsigned long long *)&d.mask[w[j]], (unsigned long long)bit);
+        }
+        return;
+    }
     for (int64_t k0 = b; k0 < e; k0 += 4 * width) {
         int32_t w[4];
 #pragma unroll
@@ -1141,25 +1155,8 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
         } else {
             d.c[v] = t;
             un.u[kUCommits] += 1;
-            const int64_t fsh = d.fshift(v);
-            for (int64_t k0 = b; k0 < e && d.light_pull != kPullOnly; k0 += 4) {
-                int32_t w[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) w[j] = k0 + j < e ? d.colidx[k0 + j] + gb : -1;
-                bool skip[4];  // committed neighbours, and class L ones when they pull
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int32_t cw = w[j] >= 0 ? d.c[w[j]] : 1;
-                    const int8_t kw = w[j] >= 0 && d.light_pull == kPullLight ? d.cls[w[j]] : (int8_t)kW;
-                    skip[j] = cw > 0 || kw == kL;
-                }
-                MapRef fm[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) fm[j] = skip[j] ? MapRef{0, 0} : map_of(d, w[j], fsh);
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if ((uint32_t)t <= fm[j].size) d.F[fm[j].pos + t - 1] = 1;
-            }
+            // a thread's own row, four entries at a time (the row-push rules above)
+            if (d.light_pull != kPullOnly) push_row(d, b, e, t, gb, d.fshift(v), 0, 1);
             un.u[kUPushEntries] += d.light_pull == kPullOnly ? 0 : e - b;
         }
         if (d.grounds) {
