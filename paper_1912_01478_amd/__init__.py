@@ -417,9 +417,10 @@ def push_microbench(n: int, count: int = 1000, nowl: bool = False, atomic: bool 
 # ---------------------------------------------------------------- serving
 
 # Device bytes per arena node slot and per CSR entry slot of a server (see ipgc_server_create):
-# per node: row start 8, graph base/index 8, state 4, color mask 8, class 1, ring start/length 8, static list 4,
-# staging 4, both segmented lists 24; per entry: column id 4, ring 4, byte map 1.
-SERVER_NODE_BYTES = 69
+# per node: row start 8, graph base/index 8, state 4, color mask 8, pending positions 4, class 1,
+# ring start/length 8, static list 4, staging 4, both segmented lists 24; per entry: column id 4,
+# ring 4, byte map 1.
+SERVER_NODE_BYTES = 73
 SERVER_ENTRY_BYTES = 9
 
 

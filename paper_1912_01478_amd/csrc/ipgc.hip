@@ -62,6 +62,7 @@ struct Workspace {
     DBuf<int8_t> cls;
     DBuf<uint8_t> F;
     DBuf<uint64_t> mask;
+    DBuf<uint32_t> pend;
     DBuf<int64_t> growptr, node_off, edge_off;  // batches: union row starts, graph offsets
     DBuf<int32_t> gbase, gidx, grounds;         // batches: per-node graph base and index, rounds per graph
     DBuf<uint64_t> ticks;
@@ -91,6 +92,7 @@ struct Workspace {
         TRY(cls.reserve(n));
         TRY(F.reserve(m + n + 64));
         TRY(mask.reserve(n));
+        TRY(pend.reserve(n));
         TRY(lower.reserve(m));
         TRY(lstart.reserve(n));
         TRY(llen.reserve(n));
@@ -102,7 +104,7 @@ struct Workspace {
         static_list.release(); seg_list0.release(); seg_list1.release(); seg_cnt.release(); hub_won.release();
         block_cnt.release(); trace.release(); lstart.release(); llen.release(); lower.release();
         seg_deg.release(); block_deg.release(); units.release(); trace_deg.release(); cls.release();
-        F.release(); mask.release(); ticks.release(); bar.release(); growptr.release(); node_off.release(); edge_off.release();
+        F.release(); mask.release(); pend.release(); ticks.release(); bar.release(); growptr.release(); node_off.release(); edge_off.release();
         gbase.release(); gidx.release(); grounds.release();
         if (ct) (void)hipFree(ct);
         if (host_ct) (void)hipHostFree(host_ct);
@@ -259,6 +261,7 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
     d.cls = ws.cls.p;
     d.F = ws.F.p;
     d.mask = ws.mask.p;
+    d.pend = ws.pend.p;
     d.lower = ws.lower.p;
     d.lstart = ws.lstart.p;
     d.llen = ws.llen.p;

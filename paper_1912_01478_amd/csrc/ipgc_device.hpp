@@ -161,6 +161,7 @@ struct DevT {
     int32_t *c;              // color state (caller's output)
     const int8_t *cls;       // class per node
     uint64_t *mask;          // per node: bit t - 1 set iff a committed neighbour has color t (t <= 64)
+    uint32_t *pend;          // class L: bit j set while row entry j's neighbour has not been seen committed
     uint8_t *F;              // byte maps for colors above 64: node v's map is bytes [rowptr[v] + v,
                              // rowptr[v + 1] + v] (byte t - 1 for color t), shifted by fshift(v)
     int32_t *lower;          // ring of smaller neighbours per W/M node (region rowptr[v] .. + d)
@@ -411,6 +412,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_init(D d, int8_t *cls, int32_t s
         const int64_t dv = b ? 0 : e - a;
         const int k = node_class(dv, d.light_max, d.hub_min);
         cls[v] = (int8_t)k;
+        d.pend[v] = k != kL ? 0u : dv >= 32 ? ~0u : (1u << dv) - 1u;
         cnt[k] += 1;
         deg[k] += dv;
     }
@@ -1127,23 +1129,55 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
         const int32_t gb = d.base(v);
         bool lose = false, done = false;
         int32_t read = 0;
-        // four neighbours per step: their ids, then their states, then the test in row order
-        for (int64_t k0 = b; k0 < e && !lose && !done; k0 += 4) {
-            int32_t u[4], cu[4];
+        if (d.light_pull == kPullOnly) {
+            // four neighbours per step: their ids, then their states, then the test in row order
+            for (int64_t k0 = b; k0 < e && !lose && !done; k0 += 4) {
+                int32_t u[4], cu[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) u[j] = k0 + j < e ? d.colidx[k0 + j] + gb : INT32_MAX;
+                for (int j = 0; j < 4; ++j) u[j] = k0 + j < e ? d.colidx[k0 + j] + gb : INT32_MAX;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) cu[j] = u[j] < v ? d.c[u[j]] : 0;
+                for (int j = 0; j < 4; ++j) cu[j] = u[j] < v ? d.c[u[j]] : 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (lose || done) continue;
-                if (u[j] >= v) {
-                    if (d.sorted || u[j] == INT32_MAX) done = true;
-                    continue;
+                for (int j = 0; j < 4; ++j) {
+                    if (lose || done) continue;
+                    if (u[j] >= v) {
+                        if (d.sorted || u[j] == INT32_MAX) done = true;
+                        continue;
+                    }
+                    ++read;
+                    lose = iabs(cu[j]) == t;
                 }
-                ++read;
-                lose = iabs(cu[j]) == t;
             }
+        } else {
+            // with pushes: only the row positions still pending (neighbours not seen committed;
+            // a committed neighbour's color has reached this node's mask), four per step, in
+            // row order; the committed ones seen now leave the set
+            const uint32_t p0 = d.pend[v];
+            uint32_t pm = p0, seen = 0;
+            while (pm && !lose && !done) {
+                int32_t jj[4], u[4], cu[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    jj[j] = pm ? __ffs(pm) - 1 : -1;
+                    pm &= pm - 1;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) u[j] = jj[j] >= 0 ? d.colidx[b + jj[j]] + gb : INT32_MAX;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) cu[j] = u[j] < v ? d.c[u[j]] : 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (lose || done) continue;
+                    if (u[j] >= v) {
+                        if (d.sorted || u[j] == INT32_MAX) done = true;
+                        continue;
+                    }
+                    ++read;
+                    lose = iabs(cu[j]) == t;
+                    if (cu[j] > 0) seen |= 1u << jj[j];
+                }
+            }
+            if (seen) d.pend[v] = p0 & ~seen;
         }
         un.u[kUConflictNodes] += 1;
         un.u[kUConflictEntries] += read;

@@ -62,6 +62,7 @@ struct AdmitJob {
 
 __global__ __launch_bounds__(256) void k_srv_admit(AdmitJob j, int32_t light_max, int32_t hub_min, int64_t *growptr,
                                                    int32_t *gbase, int32_t *gidx, int8_t *cls, int32_t *c, uint64_t *mask,
+                                                   uint32_t *pend,
                                                    int32_t *lstart, int32_t *llen, int64_t *gend, int64_t *gfshift,
                                                    int32_t *gleft, int32_t *grounds, int32_t *gerr) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(256) void k_srv_admit(AdmitJob j, int32_t light_max
         lstart[v] = 0;
         llen[v] = 0;
         mask[v] = 0;
+        pend[v] = 0;
         if (lv == n) {  // sentinel: ends the last row
             bad |= a != m;
             growptr[v] = e0 + m;
@@ -95,7 +97,9 @@ __global__ __launch_bounds__(256) void k_srv_admit(AdmitJob j, int32_t light_max
         const bool ok = a >= 0 && e >= a && e <= m;
         bad |= !ok;
         growptr[v] = e0 + a;
-        cls[v] = (int8_t)node_class(ok ? e - a : 0, light_max, hub_min);
+        const int64_t dv = ok ? e - a : 0;
+        cls[v] = (int8_t)node_class(dv, light_max, hub_min);
+        if (cls[v] == kL) pend[v] = dv >= 32 ? ~0u : (1u << dv) - 1u;
         c[v] = 0;
     }
     if (__ballot(bad) && lane_id() == 0) gerr[slot] = 1;
@@ -288,6 +292,7 @@ struct Server {
     DBuf<int64_t> growptr, gend, gfshift, seg_deg, units;
     DBuf<int32_t> colidx, gbase, gidx, c, lower, lstart, llen, static_list, seg0, seg1, seg_cnt, block_cnt, stage;
     DBuf<uint64_t> mask;
+    DBuf<uint32_t> pend;
     DBuf<int32_t> grounds, gleft, gerr;
     DBuf<int8_t> cls;
     DBuf<uint8_t> F;
@@ -358,6 +363,7 @@ int Server::create(const ipgc_server_config &cfg) {
     TRY(gidx.reserve(ncap));
     TRY(c.reserve(ncap));
     TRY(mask.reserve(ncap));
+    TRY(pend.reserve(ncap));
     TRY(cls.reserve(ncap));
     TRY(lstart.reserve(ncap));
     TRY(llen.reserve(ncap));
@@ -414,7 +420,7 @@ void Server::destroy() {
     colidx.release(); gbase.release(); gidx.release(); c.release(); lower.release(); lstart.release();
     llen.release(); static_list.release(); seg0.release(); seg1.release(); seg_cnt.release();
     block_cnt.release(); stage.release(); grounds.release(); gleft.release(); gerr.release(); cls.release();
-    F.release(); mask.release(); hub_won.release(); bar.release();
+    F.release(); mask.release(); pend.release(); hub_won.release(); bar.release();
     if (ct) (void)hipFree(ct);
     if (host_ct) (void)hipHostFree(host_ct);
     if (s) (void)hipStreamDestroy(s);
@@ -440,6 +446,7 @@ SDev Server::dev_view(int64_t nhigh, int64_t threshold) {
     d.cls = cls.p;
     d.F = F.p + kFPad;
     d.mask = mask.p;
+    d.pend = pend.p;
     d.lower = lower.p;
     d.lstart = lstart.p;
     d.llen = llen.p;
@@ -566,7 +573,7 @@ int Server::admit_staged() {
         const int64_t v0 = j.v0, e0 = j.e0, f0 = j.f0;
         const AdmitJob aj{stage.p + j.stage, j.n, j.m, e0, f0 - (e0 + v0), (int32_t)v0, slot, j.r_adm};
         const int blocks = (int)std::min<int64_t>(4096, (j.n + 1 + 255) / 256);
-        k_srv_admit<<<blocks, 256, 0, s>>>(aj, P.light_max, P.hub_min, growptr.p, gbase.p, gidx.p, cls.p, c.p, mask.p,
+        k_srv_admit<<<blocks, 256, 0, s>>>(aj, P.light_max, P.hub_min, growptr.p, gbase.p, gidx.p, cls.p, c.p, mask.p, pend.p,
                                            lstart.p, llen.p, gend.p, gfshift.p, gleft.p, grounds.p, gerr.p);
         SDev d = dev_view(nodes.high(), 0);
         const int pblocks = (int)std::min<int64_t>(8192, (j.n + 3) / 4);
