@@ -898,21 +898,25 @@ __device__ __forceinline__ void push_row_wave(const D &d, int64_t b, int64_t e, 
 // save in latency.  Kept entries are written past the ring's end, which never
 // reaches an entry not yet read: at most `read` entries are kept and the ring
 // never holds more than d entries.
+// S = 64 or 16 lanes (a wavefront, or a quarter of one) scan node v's ring; the
+// lanes of the group agree on every loop condition, and ballots are masked to
+// the group.  Quarter-wave groups read four chunks of 16 entries per pass.
 template <class D>
-__device__ bool ring_scan_wave(const D &d, int32_t v, int32_t t, int wide, Units &un) {
+__device__ bool ring_scan_group(const D &d, int32_t v, int32_t t, int wide, int S, Units &un) {
     constexpr int kPass = 4;
-    const int lane = lane_id();
+    const int lane = lane_id(), gl = lane % S;
+    const uint64_t gm = S == kWave ? ~0ull : (((1ull << S) - 1) << (lane - gl));
     const int64_t base = d.rowptr[v];
     const int32_t cap = (int32_t)(d.rowptr[v + 1] - base);
     int32_t start = d.lstart[v], len = d.llen[v];
     int32_t read = 0, kept = 0;
     bool lose = false;
-    int chunks = 1;  // the first pass reads one chunk (a loser often stops there), later passes `wide`
+    int chunks = S == kWave ? 1 : kPass;  // a wavefront's first pass reads one chunk (a loser often stops there)
     while (read < len && !lose) {
         int32_t u[kPass], cu[kPass];
 #pragma unroll
         for (int j = 0; j < kPass; ++j) {
-            const int32_t k = read + j * kWave + lane;
+            const int32_t k = read + j * S + gl;
             u[j] = -1;
             if (j < chunks && k < len) {
                 int32_t p = start + k;
@@ -927,7 +931,7 @@ __device__ bool ring_scan_wave(const D &d, int32_t v, int32_t t, int wide, Units
         for (int j = 0; j < kPass; ++j) {
             hit |= u[j] >= 0 && iabs(cu[j]) == t;
             const bool keep = u[j] >= 0 && cu[j] <= 0;  // not committed (0: uncolored in place)
-            const uint64_t km = __ballot(keep);
+            const uint64_t km = __ballot(keep) & gm;
             if (keep) {
                 int32_t p = start + len + kept + __popcll(km & lanes_below());
                 while (p >= cap) p -= cap;
@@ -935,13 +939,13 @@ __device__ bool ring_scan_wave(const D &d, int32_t v, int32_t t, int wide, Units
             }
             kept += __popcll(km);
         }
-        lose = __ballot(hit) != 0;
-        read += min(chunks * kWave, len - read);
-        chunks = wide;
+        lose = (__ballot(hit) & gm) != 0;
+        read += min(chunks * S, len - read);
+        if (S == kWave) chunks = wide;
     }
-    un.u[kUConflictEntries] += lane == 0 ? read : 0;
-    un.u[kUListWrites] += lane == 0 ? kept : 0;
-    if (lane == 0 && len > 0) {
+    un.u[kUConflictEntries] += gl == 0 ? read : 0;
+    un.u[kUListWrites] += gl == 0 ? kept : 0;
+    if (gl == 0 && len > 0) {
         int32_t s2 = start + read;
         while (s2 >= cap) s2 -= cap;
         d.lstart[v] = s2;
@@ -949,6 +953,7 @@ __device__ bool ring_scan_wave(const D &d, int32_t v, int32_t t, int wide, Units
     }
     return lose;
 }
+
 
 // Conflict test of the W/M nodes by teams of T wavefronts (T = 2, 4, 8 or 16)
 // for rounds with few of them, so a long ring is read up to T times faster
@@ -1087,35 +1092,46 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
     int T = 1;  // wavefronts per W/M node: more when there are few of them
     while (T < kRoundWaves && (int64_t)nWM * T * 2 <= nw) T *= 2;
     if (T > 1) conflict_wide_teams(d, in, os, r, un, G, T, discard, seg_base, s_cnt, s_deg);
-    for (int64_t i = gw; i < nWM && T == 1; i += nw) {
-        const bool hub = i >= nW;
-        const int32_t v = hub ? in.cv[kM].at((int32_t)(i - nW)) : in.cv[kW].at((int32_t)i);
-        const int32_t cv = d.c[v];
-        if (in.topo && cv > 0) continue;
-        const int32_t t = -cv;
-        const bool lose = ring_scan_wave(d, v, t, in.total <= kWideScanMax ? 4 : 1, un);
-        const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
-        const int q = hub ? kM : kW;
-        if (lane == 0) un.u[kUConflictNodes] += 1;
-        if (lose) {
-            if (lane == 0) {
-                if (d.racy) d.c[v] = 0;
-                const int p = atomicAdd(&s_cnt[q], 1);
-                atomicAdd(&s_deg[q], (unsigned long long)(e - b));
-                if (!discard) os.list[seg_base[q] + p] = v;
-            }
-        } else {
-            if (lane == 0) {
-                d.c[v] = t;
-                un.u[kUCommits] += 1;
-                if (d.grounds) atomicMax(&d.grounds[d.gidx[v]], r);
-                if (d.gleft) atomicSub(&d.gleft[d.gidx[v]], 1);
-            }
-            if (hub) {
-                if (lane == 0) d.hub_won[atomicAdd(&d.ct->hub_winners, 1)] = HubRec{b, e, d.fshift(v), t, d.base(v)};
+    // Without teams: a wavefront per node, or, when W nodes are many (at least four per
+    // wavefront), a quarter wavefront per W node so that four latency chains overlap.
+    const bool quarter = T == 1 && (int64_t)nW >= 4 * nw;
+    for (int ph = 0; ph < 2 && T == 1; ++ph) {
+        const int S = ph == 0 && quarter ? 16 : kWave;
+        const int64_t lo = ph == 0 ? 0 : (quarter ? nW : nWM), hi = ph == 0 && quarter ? nW : nWM;
+        const int per = kWave / S, gl = lane % S;
+        // the loop is the same for the whole wavefront; group lane / S takes item i0 + lane / S
+        for (int64_t i0 = lo + gw * per; i0 < hi; i0 += nw * per) {
+            const int64_t i = i0 + lane / S;
+            if (i >= hi) continue;
+            const bool hub = i >= nW;
+            const int32_t v = hub ? in.cv[kM].at((int32_t)(i - nW)) : in.cv[kW].at((int32_t)i);
+            const int32_t cv = d.c[v];
+            if (in.topo && cv > 0) continue;
+            const int32_t t = -cv;
+            const bool lose = ring_scan_group(d, v, t, in.total <= kWideScanMax ? 4 : 1, S, un);
+            const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
+            const int q = hub ? kM : kW;
+            if (gl == 0) un.u[kUConflictNodes] += 1;
+            if (lose) {
+                if (gl == 0) {
+                    if (d.racy) d.c[v] = 0;
+                    const int p = atomicAdd(&s_cnt[q], 1);
+                    atomicAdd(&s_deg[q], (unsigned long long)(e - b));
+                    if (!discard) os.list[seg_base[q] + p] = v;
+                }
             } else {
-                push_row_wave(d, b, e, t, d.base(v), d.fshift(v));
-                un.u[kUPushEntries] += lane == 0 ? e - b : 0;
+                if (gl == 0) {
+                    d.c[v] = t;
+                    un.u[kUCommits] += 1;
+                    if (d.grounds) atomicMax(&d.grounds[d.gidx[v]], r);
+                    if (d.gleft) atomicSub(&d.gleft[d.gidx[v]], 1);
+                }
+                if (hub) {
+                    if (gl == 0) d.hub_won[atomicAdd(&d.ct->hub_winners, 1)] = HubRec{b, e, d.fshift(v), t, d.base(v)};
+                } else {
+                    push_row(d, b, e, t, d.base(v), d.fshift(v), gl, S);
+                    un.u[kUPushEntries] += gl == 0 ? e - b : 0;
+                }
             }
         }
     }
