@@ -750,6 +750,32 @@ struct OutSegs {
 // Every uncolored node takes the smallest color >= 1 that no committed
 // neighbour holds (Section II-C with its footnote on mex; 0 marks uncolored).
 
+// First free color of W/M node v from color 65 on (its 64 mask bits are all
+// set), a wavefront over its byte map; writes the tentative color.
+template <class D>
+__device__ __forceinline__ void map_assign_wave(const D &d, int32_t v, Units &un) {
+    const int lane = lane_id();
+    const int32_t cv = d.c[v];
+    const MapRef fm = map_of(d, v, d.fshift(v));
+    // from the previous tentative color (0-based; first-fit colors only grow) or color 65
+    uint32_t st = max(cv < 0 ? (uint32_t)(-cv) - 1u : 0u, (uint32_t)kMaskColors);
+    int32_t t = (int32_t)fm.size;  // d + 1 is free if nothing smaller is
+    for (; st < fm.size; st += kWave) {
+        const uint32_t idx = st + lane;
+        const uint8_t used = idx < fm.size ? d.F[fm.pos + idx] : 0;
+        const uint64_t fz = __ballot(used == 0);
+        un.u[kUMapBytes] += lane == 0 ? kWave : 0;
+        if (fz) {
+            t = (int32_t)(st + __ffsll((unsigned long long)fz));
+            break;
+        }
+    }
+    if (lane == 0) {
+        d.c[v] = -t;
+        un.u[kUAssignNodes] += 1;
+    }
+}
+
 template <class D>
 __device__ void assign_step(const D &d, const RoundIn &in, Units &un, int G) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)G * blockDim.x;
@@ -784,39 +810,57 @@ __device__ void assign_step(const D &d, const RoundIn &in, Units &un, int G) {
         }
         un.u[kUAssignNodes] += 1;
     }
-    // classes W and M: a wavefront per node, first zero bit of the color mask, else first free
-    // byte of the byte map from color 65 on
+    // classes W and M.  Large rounds (at least four W/M nodes per wavefront): a thread per node
+    // for the first zero bit of the color mask; nodes whose mask is full (64 colors taken) are
+    // queued in shared memory and each gets a wavefront for its byte map from color 65 on (the
+    // loop bounds depend on the workgroup only).  Small rounds: a wavefront per node.
+    __shared__ int32_t s_full[kRoundBlock];
+    __shared__ int s_nfull;
     const int32_t nW = in.cv[kW].total, nWM = nW + in.cv[kM].total;
-    for (int64_t i = gw; i < nWM; i += nw) {
-        const int32_t v = i < nW ? in.cv[kW].at((int32_t)i) : in.cv[kM].at((int32_t)(i - nW));
-        const int32_t cv = d.c[v];
-        if (in.topo && cv > 0) continue;
-        const uint64_t free = ~d.mask[v];
-        un.u[kUMapBytes] += lane == 0 ? 8 : 0;
-        if (free) {
-            if (lane == 0) {
-                d.c[v] = -__ffsll((unsigned long long)free);
-                un.u[kUAssignNodes] += 1;
+    if ((int64_t)nWM >= 4 * nw) {
+        if (threadIdx.x == 0) s_nfull = 0;
+        __syncthreads();
+        for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < nWM; i0 += nt) {
+            const int64_t i = i0 + threadIdx.x;
+            int32_t v = -1;
+            bool full = false;
+            if (i < nWM) {
+                v = i < nW ? in.cv[kW].at((int32_t)i) : in.cv[kM].at((int32_t)(i - nW));
+                const int32_t cv = d.c[v];
+                if (!(in.topo && cv > 0)) {
+                    const uint64_t free = ~d.mask[v];
+                    un.u[kUMapBytes] += 8;
+                    if (free) {
+                        d.c[v] = -__ffsll((unsigned long long)free);
+                        un.u[kUAssignNodes] += 1;
+                    } else {
+                        full = true;
+                    }
+                }
             }
-            continue;
+            const int pos = block_append(full, &s_nfull);
+            if (full) s_full[pos] = v;
+            __syncthreads();
+            for (int k = threadIdx.x / kWave; k < s_nfull; k += kRoundWaves) map_assign_wave(d, s_full[k], un);
+            __syncthreads();
+            if (threadIdx.x == 0) s_nfull = 0;
+            __syncthreads();
         }
-        const MapRef fm = map_of(d, v, d.fshift(v));
-        // from the previous tentative color (0-based; first-fit colors only grow) or color 65
-        uint32_t s = max(cv < 0 ? (uint32_t)(-cv) - 1u : 0u, (uint32_t)kMaskColors);
-        int32_t t = (int32_t)fm.size;  // d + 1 is free if nothing smaller is
-        for (; s < fm.size; s += kWave) {
-            const uint32_t idx = s + lane;
-            const uint8_t used = idx < fm.size ? d.F[fm.pos + idx] : 0;
-            const uint64_t fz = __ballot(used == 0);
-            un.u[kUMapBytes] += lane == 0 ? kWave : 0;
-            if (fz) {
-                t = (int32_t)(s + __ffsll((unsigned long long)fz));
-                break;
+    } else {
+        for (int64_t i = gw; i < nWM; i += nw) {
+            const int32_t v = i < nW ? in.cv[kW].at((int32_t)i) : in.cv[kM].at((int32_t)(i - nW));
+            const int32_t cv = d.c[v];
+            if (in.topo && cv > 0) continue;
+            const uint64_t free = ~d.mask[v];
+            un.u[kUMapBytes] += lane == 0 ? 8 : 0;
+            if (free) {
+                if (lane == 0) {
+                    d.c[v] = -__ffsll((unsigned long long)free);
+                    un.u[kUAssignNodes] += 1;
+                }
+                continue;
             }
-        }
-        if (lane == 0) {
-            d.c[v] = -t;
-            un.u[kUAssignNodes] += 1;
+            map_assign_wave(d, v, un);
         }
     }
     un.fold();
@@ -1096,7 +1140,8 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
     // wavefront), a quarter wavefront per W node so that four latency chains overlap.
     const bool quarter = T == 1 && (int64_t)nW >= 4 * nw;
     for (int ph = 0; ph < 2 && T == 1; ++ph) {
-        const int S = ph == 0 && quarter ? 16 : kWave;
+        const int64_t cnt = ph == 0 && quarter ? nW : nWM - nW;  // nodes of this phase's class(es)
+        const int S = ph == 0 && !quarter ? kWave : cnt >= 8 * nw ? 8 : cnt >= 4 * nw ? 16 : kWave;
         const int64_t lo = ph == 0 ? 0 : (quarter ? nW : nWM), hi = ph == 0 && quarter ? nW : nWM;
         const int per = kWave / S, gl = lane % S;
         // the loop is the same for the whole wavefront; group lane / S takes item i0 + lane / S
