@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
-# Algorithmic bytes of the method (SURVEY-style per-unit figures):
+# Algorithmic bytes of the method (per-unit figures of the data-driven rounds of Section II-C):
 # per round r, 36 bytes per active node and 16 bytes per row entry of an active node:
 #   assign   worklist entry 4 + row bounds 8 + tentative write 4 per node; column index 4 +
 #            neighbour color 4 per entry
