@@ -441,7 +441,7 @@ def main_push_microbench(args, pkg, np):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; --gpus %d is not supported (use --gpus 1)" % args.gpus,
+        print("bench.py: the library and this benchmark run on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
