@@ -63,6 +63,18 @@ def test_closed_forms(g, mode):
     P.check_coloring(g.rowptr, g.colidx, col, rounds)
 
 
+@pytest.mark.parametrize("hub_min", [0, 40])
+@pytest.mark.parametrize("k", [63, 64, 65, 66, 129])
+def test_color_mask_boundary(k, hub_min):
+    """K_k needs colors 1..k, one node committing per round: the last colors sit at the edge of the
+    64-bit color masks (64, 65) or well past it (129, in the byte maps).  Every node has degree
+    k - 1 > 32: a wavefront node that pushes its own row (hub_min 0: 1024) or a hub whose row the
+    whole grid pushes (hub_min 40)."""
+    g = gg.complete(k)
+    col, rounds, _, _ = assert_parity(g, "hybrid", hub_min_degree=hub_min)
+    assert sorted(col.tolist()) == list(range(1, k + 1)) and rounds == k
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_hand_traced_golden(mode):
     from tests.test_oracle_pins import _read_hand_traced
