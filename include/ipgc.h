@@ -48,8 +48,9 @@ typedef enum ipgc_status {
     IPGC_ETOOBIG = -2,  /* n or m does not fit the int32 CSR */
     IPGC_EBADCSR = -3,  /* rowptr[0] != 0, rowptr[n] != m, decreasing rowptr, or id out of [0, n) */
     IPGC_ENOMEM = -4,   /* device workspace allocation failed */
-    IPGC_EHIP = -5,     /* a HIP runtime call failed */
-    IPGC_ELIMIT = -6    /* the round limit was reached (cannot happen for valid input: rounds <= n) */
+    IPGC_EHIP = -5,     /* a HIP runtime call failed, or a grid-barrier wait exceeded its time limit */
+    IPGC_ELIMIT = -6,   /* the round limit was reached (cannot happen for valid input: rounds <= n) */
+    IPGC_ECANCELED = -7 /* a server job was cancelled before it finished (ipgc_server_cancel) */
 } ipgc_status;
 
 /* Round schedules (Section IV).  TOPOLOGY runs every round as a sweep over all
@@ -67,11 +68,23 @@ typedef enum ipgc_mode {
 } ipgc_mode;
 
 /* Validation levels.  A column id outside [0, n) would make the kernels read
- * outside the color array, so the default checks every id. */
+ * outside the color array, so the default checks every id.
+ *
+ * The method colors an undirected simple graph, and the experiments of Section V
+ * remove self-loops and multi-edges first.  The kernels learn a node's forbidden
+ * colors from pushes along its neighbours' rows, so on a CSR that is not
+ * symmetric they would not follow the definition (which reads the node's own
+ * row).  IPGC_VALIDATE_FULL rejects such input: every entry (v, u) needs its
+ * reverse (u, v), and no row may hold v itself or the same id twice.  It sorts a
+ * copy of every row in the library's workspace (rows already sorted are copied)
+ * and looks each reverse entry up by binary search: O(m log max_degree) work on
+ * the device, off the coloring's own path. */
 enum {
     IPGC_VALIDATE_DEFAULT = 0, /* same as IPGC_VALIDATE_RANGES */
     IPGC_VALIDATE_NONE = 1,    /* trust the caller: only rowptr[0] == 0 and rowptr[n] == m are checked */
-    IPGC_VALIDATE_RANGES = 2   /* also rowptr non-decreasing and every column id in [0, n) */
+    IPGC_VALIDATE_RANGES = 2,  /* also rowptr non-decreasing and every column id in [0, n) */
+    IPGC_VALIDATE_FULL = 3     /* also a simple symmetric graph: no self-loop, no duplicate entry in a row,
+                                  and (u, v) present for every entry (v, u); IPGC_EBADCSR otherwise */
 };
 
 /* Kernel kinds that ipgc_profile can time (see ipgc_kernel_name) and work
@@ -119,6 +132,11 @@ typedef struct ipgc_options {
                                   only this many workgroups stay in the cooperative round loop (cheaper
                                   grid barriers for the long tail of small rounds; 0: default, negative:
                                   all workgroups stay) */
+    int32_t barrier_timeout_ms; /* limit on every grid-barrier wait of a cooperative launch: a workgroup
+                                  that waits longer gives up, every other one leaves at its next wait,
+                                  and the call returns IPGC_EHIP (0: default 60000; -1: give up at the
+                                  first wait that does not complete at once, to exercise that path) */
+    int32_t reserved;          /* must be 0 */
 } ipgc_options;
 
 /* Option flags. */
@@ -250,6 +268,7 @@ typedef struct ipgc_job_result {
 
 typedef struct ipgc_server_stats {
     int64_t steps;          /* ipgc_server_step calls that ran rounds */
+    int64_t cancelled;      /* jobs cancelled before they finished */
     int64_t rounds;         /* rounds run (over the union) */
     int64_t submitted, admitted, completed;
     int64_t resident;       /* jobs resident now */
@@ -290,6 +309,28 @@ int ipgc_server_poll(ipgc_server *server, ipgc_job_result *results, int64_t capa
 
 int ipgc_server_stats_get(const ipgc_server *server, ipgc_server_stats *stats);
 
+/*
+ * Runs steps until job job_id has finished, then takes its result out of the
+ * list of finished jobs (so ipgc_server_poll will not report it) and stores it
+ * in *result.  The job's out_colors are filled if its status is IPGC_OK.  Jobs
+ * that finish on the way stay in the list for ipgc_server_poll.  Returns
+ * IPGC_EINVAL if no job with that id is queued, resident or finished and not
+ * yet reported; errors of ipgc_server_step are returned as they occur.
+ */
+int ipgc_server_wait(ipgc_server *server, int64_t job_id, ipgc_job_result *result);
+
+/*
+ * Cancels a job that has not finished.  A queued job is dropped; a job whose
+ * upload is under way is dropped once the upload has ended (the call waits for
+ * it); a resident job leaves the union before the next round, and its arena
+ * ranges are freed.  Its out_colors are never written, and it is reported
+ * (ipgc_server_poll / ipgc_server_wait) with status IPGC_ECANCELED and rounds
+ * -1.  Every other job's result is unchanged: jobs in the union never read one
+ * another's state.  Returns IPGC_EINVAL if the job has already finished or no
+ * such job exists.
+ */
+int ipgc_server_cancel(ipgc_server *server, int64_t job_id);
+
 /* Frees the arena.  Queued and resident jobs are dropped. */
 void ipgc_server_destroy(ipgc_server *server);
 
@@ -320,8 +361,10 @@ int ipgc_bfs(const int32_t *csr_rowptr, const int32_t *csr_colidx, int64_t n, in
  * worklist (nowl = 0: Push_WL) or over every id (nowl = 1: Push_NoWL), until
  * the worklist is empty.  atomic = 0 pushes with per-workgroup segments and no
  * global atomic (as the coloring kernels do); atomic = 1 fills one global
- * worklist with one atomicAdd per wavefront.  One cooperative launch with a
- * grid barrier per iteration.  HOST arrays of `capacity` entries (at least
+ * worklist with one atomicAdd per wavefront.  One kernel launch per
+ * iteration: the launch boundary separates iterations, and the first
+ * workgroup of each launch stamps the device clock, so an iteration's time
+ * includes its launch.  HOST arrays of `capacity` entries (at least
  * ceil(n/count) + 2) receive the device wall clock at the start of every
  * iteration plus one at the end (ticks) and the worklist size at the start of
  * every iteration (sizes); iterations receives the number of non-empty
@@ -348,6 +391,24 @@ int ipgc_version(void);
 /* Releases the cached per-device workspaces (of the coloring and BFS entry
  * points).  Optional; safe to call anytime no other call is in flight. */
 void ipgc_release_workspaces(void);
+
+/*
+ * Device memory hook.  By default the library takes device memory with
+ * hipMalloc and returns it with hipFree: its cached workspaces (which only
+ * grow) and the arena of each server (sized at ipgc_server_create).  A caller
+ * that manages device memory itself (a framework's caching allocator, a
+ * memory budget, a test that injects failures) installs alloc/free here:
+ * alloc(bytes, device, user) returns a device pointer on `device` aligned to
+ * at least 256 bytes, or NULL, which the library reports as IPGC_ENOMEM after
+ * freeing what the failing call had taken; free(ptr, bytes, device, user)
+ * takes back a pointer that alloc returned (with the same size).  Memory is
+ * always returned to the hook pair that gave it, even after the hook has been
+ * replaced.  Both NULL restore hipMalloc/hipFree.  IPGC_EINVAL if exactly one
+ * of them is NULL.  Install the hook when no other library call is in flight.
+ */
+typedef void *(*ipgc_alloc_fn)(uint64_t bytes, int device, void *user);
+typedef void (*ipgc_free_fn)(void *ptr, uint64_t bytes, int device, void *user);
+int ipgc_set_allocator(ipgc_alloc_fn alloc, ipgc_free_fn free_fn, void *user);
 
 #ifdef __cplusplus
 }

@@ -8,8 +8,10 @@ import of :func:`library` raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -26,15 +28,18 @@ MODES = {"topology": MODE_TOPOLOGY, "data": MODE_DATA, "hybrid": MODE_HYBRID, "r
 VALIDATE_DEFAULT = 0
 VALIDATE_NONE = 1
 VALIDATE_RANGES = 2
+VALIDATE_FULL = 3
 
+OK, EINVAL, ETOOBIG, EBADCSR, ENOMEM, EHIP, ELIMIT, ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS = {0: "IPGC_OK", -1: "IPGC_EINVAL", -2: "IPGC_ETOOBIG", -3: "IPGC_EBADCSR", -4: "IPGC_ENOMEM",
-          -5: "IPGC_EHIP", -6: "IPGC_ELIMIT"}
+          -5: "IPGC_EHIP", -6: "IPGC_ELIMIT", -7: "IPGC_ECANCELED"}
 
 # Every symbol the header declares; the tests check that the library exports all of them.
 EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_color_graphs_batched", "ipgc_last_error",
            "ipgc_kernel_name", "ipgc_unit_name", "ipgc_version", "ipgc_release_workspaces", "ipgc_server_create",
            "ipgc_server_submit", "ipgc_server_step", "ipgc_server_poll", "ipgc_server_stats_get",
-           "ipgc_server_destroy", "ipgc_push_microbench", "ipgc_bfs")
+           "ipgc_server_destroy", "ipgc_server_wait", "ipgc_server_cancel", "ipgc_set_allocator",
+           "ipgc_push_microbench", "ipgc_bfs")
 FLAG_STEPPED = 1
 FLAG_LIGHT_PULL = 2
 FLAG_LIGHT_PUSH = 4
@@ -75,7 +80,8 @@ class Options(ctypes.Structure):
     _fields_ = [("threshold", ctypes.c_int64), ("light_max_degree", ctypes.c_int32),
                 ("hub_min_degree", ctypes.c_int32), ("validate", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("profile", ctypes.POINTER(Profile)), ("workgroups", ctypes.c_int32),
-                ("tail_workgroups", ctypes.c_int32)]
+                ("tail_workgroups", ctypes.c_int32), ("barrier_timeout_ms", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -92,7 +98,8 @@ class JobResult(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     """Mirror of ``ipgc_server_stats``."""
-    _fields_ = [(k, ctypes.c_int64) for k in ("steps", "rounds", "submitted", "admitted", "completed", "resident",
+    _fields_ = [(k, ctypes.c_int64) for k in ("steps", "cancelled", "rounds", "submitted", "admitted", "completed",
+                                              "resident",
                                               "queued", "resident_nodes", "resident_edges", "peak_resident",
                                               "arena_bytes")] + [("units", ctypes.c_int64 * 16)]
 
@@ -136,6 +143,12 @@ def library() -> ctypes.CDLL:
         lib.ipgc_server_stats_get.argtypes = [srv, ctypes.POINTER(ServerStats)]
         lib.ipgc_server_destroy.restype = None
         lib.ipgc_server_destroy.argtypes = [srv]
+        lib.ipgc_server_wait.restype = i32
+        lib.ipgc_server_wait.argtypes = [srv, i64, ctypes.POINTER(JobResult)]
+        lib.ipgc_server_cancel.restype = i32
+        lib.ipgc_server_cancel.argtypes = [srv, i64]
+        lib.ipgc_set_allocator.restype = i32
+        lib.ipgc_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
         lib.ipgc_bfs.restype = i32
         lib.ipgc_bfs.argtypes = [vp, vp, i64, i64, i64, i32, ctypes.POINTER(Options), vp, vp,
                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Trace)]
@@ -153,7 +166,77 @@ def library() -> ctypes.CDLL:
         lib.ipgc_release_workspaces.restype = None
         lib.ipgc_release_workspaces.argtypes = []
         _lib = lib
+        atexit.register(_release_at_exit)
     return _lib
+
+
+# Device memory hook (ipgc_set_allocator): alloc(bytes, device, user) -> pointer or NULL,
+# free(ptr, bytes, device, user).
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p)
+_hooks = []  # every callback pair ever installed stays alive: memory it gave is returned through it
+
+
+def set_allocator(alloc=None, free=None) -> None:
+    """Route the library's device allocations (workspaces, server arenas) through Python
+    callables: ``alloc(nbytes, device) -> int`` returns a device pointer (0 for failure, which
+    the library reports as IPGC_ENOMEM); ``free(ptr, nbytes, device)`` takes one back.  Both
+    None restores hipMalloc / hipFree.  Memory goes back to the pair that gave it."""
+    lib = library()
+    if (alloc is None) != (free is None):
+        raise ValueError("set_allocator takes both callables or neither")
+    if alloc is None:
+        _check(lib.ipgc_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+
+    def _alloc(nbytes, device, _user):
+        try:
+            return int(alloc(int(nbytes), int(device)) or 0) or None
+        except Exception:
+            return None
+
+    def _free(ptr, nbytes, device, _user):
+        try:
+            free(int(ptr), int(nbytes), int(device))
+        except Exception:
+            pass
+
+    pair = (ALLOC_FN(_alloc), FREE_FN(_free))
+    _hooks.append(pair)
+    _check(lib.ipgc_set_allocator(pair[0], pair[1], None))
+
+
+def torch_allocator():
+    """(alloc, free) callables that take the library's device memory from PyTorch's caching
+    allocator, for ``set_allocator``."""
+    import torch
+
+    def alloc(nbytes, device):
+        return torch.cuda.caching_allocator_alloc(nbytes, device)
+
+    def free(ptr, nbytes, device):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, free
+
+
+_servers = weakref.WeakSet()  # open servers, closed before the process exits
+
+
+def _release_at_exit():
+    """Returns the device memory, pinned host memory and events the library holds before the
+    interpreter, the HIP runtime and any profiler loaded into the process shut down."""
+    for srv in list(_servers):
+        try:
+            srv.close()
+        except Exception:
+            pass
+    if _lib is not None:
+        try:
+            _lib.ipgc_release_workspaces()
+            _lib.ipgc_set_allocator(ALLOC_FN(), FREE_FN(), None)
+        except Exception:
+            pass
 
 
 def _check(rc: int):
@@ -188,7 +271,8 @@ class _Call:
     """Marshalled options, optional profile and optional trace of one library call."""
 
     def __init__(self, threshold, light_max_degree, hub_min_degree, validate, stepped, trace, trace_cap,
-                 profile_mask, timeline, workgroups=0, light="auto", racy=False, tail_workgroups=0):
+                 profile_mask, timeline, workgroups=0, light="auto", racy=False, tail_workgroups=0,
+                 barrier_timeout_ms=0):
         self.prof = None
         if profile_mask or timeline:
             self.prof = Profile(int(profile_mask))
@@ -199,7 +283,7 @@ class _Call:
         self.opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), int(validate),
                             (FLAG_STEPPED if stepped else 0) | LIGHT[light] | (FLAG_RACY if racy else 0),
                             ctypes.pointer(self.prof) if self.prof is not None else None, int(workgroups),
-                            int(tail_workgroups))
+                            int(tail_workgroups), int(barrier_timeout_ms), 0)
         self.tr = None
         if trace:
             cap = max(1, min(int(trace_cap), TRACE_CAPACITY))
@@ -228,7 +312,7 @@ def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_
                 hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT, stepped: bool = False, out=None,
                 stream=None, trace: bool = False, profile_mask: int = 0, timeline: int = 0,
                 workgroups: int = 0, light: str = "auto", racy: bool = False,
-                tail_workgroups: int = 0) -> Coloring:
+                tail_workgroups: int = 0, barrier_timeout_ms: int = 0) -> Coloring:
     """Color the symmetric CSR graph (``rowptr``: int32[n+1], ``colidx``: int32[m], both on the
     HIP device) and return the 1-based colors and round count.  ``mode`` is "topology", "data"
     or "hybrid"; ``threshold`` is H for hybrid rounds (0: floor(6n/10)).  ``stepped`` runs one
@@ -240,7 +324,9 @@ def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_
     for the small data-driven rounds at the end (0: default, negative: all); ``light`` is "pull",
     "push" or "auto" (how nodes of degree <= light_max_degree learn their neighbours' colors);
     ``racy`` selects the in-place mode (a proper coloring that depends on timing, not the
-    synchronous one)."""
+    synchronous one); ``barrier_timeout_ms`` bounds every grid-barrier wait (0: 60 s; -1: give up
+    at once, which exercises the error path).  ``validate`` is VALIDATE_NONE, _RANGES (default) or
+    _FULL (also a simple symmetric graph)."""
     import torch
 
     if rowptr.dtype != torch.int32 or colidx.dtype != torch.int32:
@@ -258,7 +344,7 @@ def color_graph(rowptr, colidx, mode="hybrid", *, threshold: int = 0, light_max_
     elif out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() or out.device != rowptr.device:
         raise ValueError("out must be a contiguous int32 tensor of n entries on the graph's device")
     call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, n, profile_mask, timeline,
-                 workgroups, light, racy, tail_workgroups)
+                 workgroups, light, racy, tail_workgroups, barrier_timeout_ms)
     rounds = ctypes.c_int32(-1)
     if stream is None:
         stream = torch.cuda.current_stream(rowptr.device)
@@ -315,7 +401,7 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
                          light_max_degree: int = 0, hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT,
                          stepped: bool = False, out=None, stream=None, trace: bool = False,
                          profile_mask: int = 0, workgroups: int = 0, light: str = "auto",
-                         racy: bool = False, tail_workgroups: int = 0) -> BatchColoring:
+                         racy: bool = False, tail_workgroups: int = 0, barrier_timeout_ms: int = 0) -> BatchColoring:
     """Color many graphs in one launch.  ``rowptr_packed`` (int32[N+G]) and ``colidx_packed``
     (int32[M]) are device tensors in the layout of ``pack_graphs``; ``node_off`` and ``edge_off``
     (G+1 int64 each) are host arrays.  Each graph gets the coloring and round count it gets alone.
@@ -343,7 +429,7 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
     elif out.dtype != torch.int32 or out.numel() != N or not out.is_contiguous() or out.device != dev:
         raise ValueError("out must be a contiguous int32 tensor of N entries on the batch's device")
     call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, N, profile_mask, 0, workgroups,
-                 light, racy, tail_workgroups)
+                 light, racy, tail_workgroups, barrier_timeout_ms)
     rounds = np.full(max(G, 1), -1, dtype=np.int32)
     if stream is None:
         stream = torch.cuda.current_stream(dev)
@@ -366,7 +452,8 @@ class BfsResult:
 
 
 def bfs(rowptr, colidx, source: int, mode="hybrid", *, threshold: int = 0, workgroups: int = 0,
-        validate: int = VALIDATE_DEFAULT, out=None, stream=None, trace: bool = False) -> BfsResult:
+        validate: int = VALIDATE_DEFAULT, out=None, stream=None, trace: bool = False,
+        barrier_timeout_ms: int = 0) -> BfsResult:
     """Breadth-first search from `source` on the device CSR under the keep-the-worklist hybrid
     schedule (``ipgc_bfs``)."""
     import torch
@@ -376,7 +463,8 @@ def bfs(rowptr, colidx, source: int, mode="hybrid", *, threshold: int = 0, workg
     n, m = rowptr.numel() - 1, colidx.numel()
     if out is None:
         out = torch.empty(max(n, 0), dtype=torch.int32, device=rowptr.device)
-    call = _Call(threshold, 0, 0, validate, False, trace, max(n, 1), 0, 0, workgroups)
+    call = _Call(threshold, 0, 0, validate, False, trace, max(n, 1), 0, 0, workgroups,
+                 barrier_timeout_ms=barrier_timeout_ms)
     levels = ctypes.c_int32(-1)
     if stream is None:
         stream = torch.cuda.current_stream(rowptr.device)
@@ -439,14 +527,17 @@ class Server:
 
     def __init__(self, node_capacity: int, edge_capacity: int, max_jobs: int = 4096, rounds_per_step: int = 0,
                  mode="hybrid", threshold: int = 0, light_max_degree: int = 0, hub_min_degree: int = 0,
-                 workgroups: int = 0, light: str = "auto", racy: bool = False, tail_workgroups: int = 0):
-        opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), VALIDATE_DEFAULT,
-                       LIGHT[light] | (FLAG_RACY if racy else 0), None, int(workgroups), int(tail_workgroups))
+                 workgroups: int = 0, light: str = "auto", racy: bool = False, tail_workgroups: int = 0,
+                 validate: int = VALIDATE_DEFAULT, barrier_timeout_ms: int = 0):
+        opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), int(validate),
+                       LIGHT[light] | (FLAG_RACY if racy else 0), None, int(workgroups), int(tail_workgroups),
+                       int(barrier_timeout_ms), 0)
         cfg = ServerConfig(int(node_capacity), int(edge_capacity), int(max_jobs), int(rounds_per_step), _mode(mode),
                            0, opts)
         self._h = ctypes.c_void_p()
         _check(library().ipgc_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
         self._jobs = {}  # job id -> (rowptr, colidx, out) kept alive until the job is polled
+        _servers.add(self)
 
     @staticmethod
     def capacity_for(budget_bytes: int, avg_degree: float):
@@ -483,6 +574,18 @@ class Server:
             if cnt.value < 256:
                 return out
 
+    def wait(self, job_id: int) -> JobDone:
+        """Runs steps until job ``job_id`` finishes and returns its result (which poll() then
+        no longer reports)."""
+        r = JobResult()
+        _check(library().ipgc_server_wait(self._h, int(job_id), ctypes.byref(r)))
+        _, _, colors = self._jobs.pop(r.job_id)
+        return JobDone(r.job_id, r.status, r.rounds, colors if r.status == 0 else None)
+
+    def cancel(self, job_id: int) -> None:
+        """Cancels an unfinished job; it is reported with status ECANCELED."""
+        _check(library().ipgc_server_cancel(self._h, int(job_id)))
+
     def stats(self) -> dict:
         st = ServerStats()
         _check(library().ipgc_server_stats_get(self._h, ctypes.byref(st)))
@@ -495,6 +598,7 @@ class Server:
         if self._h:
             library().ipgc_server_destroy(self._h)
             self._h = ctypes.c_void_p()
+        _servers.discard(self)
 
     def __enter__(self):
         return self

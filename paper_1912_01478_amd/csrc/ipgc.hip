@@ -44,6 +44,39 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
+// ------------------------------------------------------------ device memory
+
+namespace {
+std::mutex g_alloc_mutex;
+AllocOwner g_alloc;  // the installed hook (null functions: hipMalloc / hipFree)
+}  // namespace
+
+int dev_alloc(void **p, size_t bytes, AllocOwner *owner) {
+    *p = nullptr;
+    AllocOwner o;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mutex);
+        o = g_alloc;
+    }
+    HIP_TRY(hipGetDevice(&o.device));
+    if (o.alloc) {
+        *p = o.alloc((uint64_t)bytes, o.device, o.user);
+        if (!*p) return fail(IPGC_ENOMEM, "device allocation of %llu bytes failed (allocation hook)", (unsigned long long)bytes);
+    } else if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(IPGC_ENOMEM, "device allocation of %llu bytes failed", (unsigned long long)bytes);
+    }
+    *owner = o;
+    return IPGC_OK;
+}
+
+void dev_free(void *p, size_t bytes, const AllocOwner &owner) {
+    if (!p) return;
+    if (owner.free) owner.free(p, (uint64_t)bytes, owner.device, owner.user);
+    else (void)hipFree(p);
+}
+
 namespace {
 
 constexpr int kPrepSpanMin = 2048;  // nodes per preparation workgroup (at least)
@@ -67,16 +100,19 @@ struct Workspace {
     DBuf<int32_t> gbase, gidx, grounds;         // batches: per-node graph base and index, rounds per graph
     DBuf<uint64_t> ticks;
     DBuf<Barrier> bar;
-    Counters *ct = nullptr;
+    DBuf<Counters> ctb;
+    DBuf<int32_t> sorted_rows;  // IPGC_VALIDATE_FULL: every row sorted (m entries)
+    Counters *ct = nullptr;       // ctb.p
     Counters *host_ct = nullptr;  // pinned
     std::vector<hipEvent_t> events;
     int coop_blocks = -1;  // co-resident round workgroups on this device (0: no cooperative launch)
 
     int reserve(int64_t n, int64_t m, int grid, int prep_grid) {
         if (!ct) {
-            HIP_TRY(hipMalloc(&ct, sizeof(Counters)));
-            HIP_TRY(hipHostMalloc(&host_ct, sizeof(Counters), hipHostMallocDefault));
+            TRY(ctb.reserve(1));
+            ct = ctb.p;
         }
+        if (!host_ct) HIP_TRY(hipHostMalloc(&host_ct, sizeof(Counters), hipHostMallocDefault));
         const int64_t seg = n + (int64_t)kNumClasses * grid * (kRoundBlock + 1);
         TRY(static_list.reserve(n));
         TRY(seg_list0.reserve(seg));
@@ -105,8 +141,7 @@ struct Workspace {
         block_cnt.release(); trace.release(); lstart.release(); llen.release(); lower.release();
         seg_deg.release(); block_deg.release(); units.release(); trace_deg.release(); cls.release();
         F.release(); mask.release(); pend.release(); ticks.release(); bar.release(); growptr.release(); node_off.release(); edge_off.release();
-        gbase.release(); gidx.release(); grounds.release();
-        if (ct) (void)hipFree(ct);
+        gbase.release(); gidx.release(); grounds.release(); ctb.release(); sorted_rows.release();
         if (host_ct) (void)hipHostFree(host_ct);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         *this = Workspace();
@@ -195,8 +230,12 @@ int parse_options(const ipgc_options *opt, int mode, Params *p) {
         return fail(IPGC_EINVAL, "light_max_degree %d outside 1..%d", p->light_max, kLightMaxLimit);
     if (p->hub_min <= p->light_max)
         return fail(IPGC_EINVAL, "hub_min_degree %d must exceed light_max_degree %d", p->hub_min, p->light_max);
-    if (o.validate < IPGC_VALIDATE_DEFAULT || o.validate > IPGC_VALIDATE_RANGES)
+    if (o.validate < IPGC_VALIDATE_DEFAULT || o.validate > IPGC_VALIDATE_FULL)
         return fail(IPGC_EINVAL, "unknown validate level %d", o.validate);
+    if (o.reserved != 0) return fail(IPGC_EINVAL, "ipgc_options.reserved must be 0");
+    if (o.barrier_timeout_ms < -1) return fail(IPGC_EINVAL, "barrier_timeout_ms %d below -1", o.barrier_timeout_ms);
+    p->barrier_ms = o.barrier_timeout_ms == 0 ? 60000 : o.barrier_timeout_ms;
+    p->full = o.validate == IPGC_VALIDATE_FULL;
     if (o.flags & ~(IPGC_FLAG_STEPPED | IPGC_FLAG_LIGHT_PULL | IPGC_FLAG_LIGHT_PUSH | IPGC_FLAG_RACY))
         return fail(IPGC_EINVAL, "unknown flags 0x%x", o.flags);
     if ((o.flags & IPGC_FLAG_LIGHT_PULL) && (o.flags & IPGC_FLAG_LIGHT_PUSH))
@@ -226,6 +265,23 @@ int parse_options(const ipgc_options *opt, int mode, Params *p) {
     return IPGC_OK;
 }
 
+int full_check_verdict(int bits) {
+    if (bits & kFullSelfLoop)
+        return fail(IPGC_EBADCSR, "a row holds its own node (a self-loop); full validation takes simple graphs");
+    if (bits & kFullDuplicate)
+        return fail(IPGC_EBADCSR, "a row holds the same id twice (a duplicate entry); full validation takes simple graphs");
+    if (bits & kFullAsymmetric)
+        return fail(IPGC_EBADCSR, "an entry (v, u) has no reverse entry (u, v): the CSR is not symmetric");
+    return IPGC_OK;
+}
+
+int barrier_limit_ticks(int dev, int barrier_ms, uint64_t *ticks) {
+    int khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    *ticks = barrier_ms < 0 ? 0 : (uint64_t)barrier_ms * (uint64_t)std::max(khz, 1);
+    return IPGC_OK;
+}
+
 namespace {
 
 Workspace &workspace(int dev) {
@@ -240,6 +296,22 @@ int round_grid(Workspace &ws, int dev, const Params &P, int64_t n, int *grid, in
     const int64_t want = P.workgroups > 0 ? P.workgroups : (n + 4 * kRoundBlock - 1) / (4 * kRoundBlock);
     *grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, *coop > 0 ? *coop : kMaxRoundBlocks));
     return IPGC_OK;
+}
+
+// IPGC_VALIDATE_FULL on a graph whose row pointers and ids have passed their
+// checks: sorted copies of the rows in the workspace, then self-loops,
+// repeated ids and missing reverse entries.
+template <typename Off>
+int check_full(Workspace &ws, hipStream_t s, const DevT<Off> &d, int64_t n, int64_t m) {
+    TRY(ws.sorted_rows.reserve(std::max<int64_t>(m, 1)));
+    HIP_TRY(hipMemsetAsync(&ws.ct->bad_full, 0, sizeof(int32_t), s));
+    const int sort_grid = (int)std::min<int64_t>(n, 65536);
+    k_full_sort<<<sort_grid, kSortBlock, 0, s>>>(d, 0, n, ws.sorted_rows.p, nullptr);
+    k_full_check<<<(int)std::min<int64_t>(16384, (n + 3) / 4), kPrepBlock, 0, s>>>(d, 0, n, ws.sorted_rows.p,
+                                                                                   &ws.ct->bad_full, nullptr);
+    HIP_TRY(hipGetLastError());
+    TRY(read_counters(ws, s));
+    return full_check_verdict(ws.host_ct->bad_full);
 }
 
 // Everything after the input is in place: d.rowptr, d.colidx, d.c and (for a
@@ -290,6 +362,7 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
     d.hub_min = P.hub_min;
     d.sorted = 0;
     d.grid = grid;
+    TRY(barrier_limit_ticks(dev, P.barrier_ms, &d.bar_limit));
     if (prof && prof->phase_ticks && prof->phase_capacity > 0) {
         TRY(ws.ticks.reserve(prof->phase_capacity));
         HIP_TRY(hipMemsetAsync(ws.ticks.p, 0, sizeof(uint64_t) * prof->phase_capacity, s));
@@ -333,6 +406,7 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
         if (ws.host_ct->bad_ids) return fail(IPGC_EBADCSR, "a column id is outside [0, n)");
     }
     d.sorted = P.check_ids && !ws.host_ct->unsorted;
+    if (P.full) TRY(check_full(ws, s, d, n, m));
 
     // Rounds: at most n (the worklist shrinks every round), plus the start of the one that finds it empty.
     if (coop > 0) {
@@ -360,7 +434,14 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
             if (ws.host_ct->finished) break;
         }
     }
-    if (!ws.host_ct->finished) return fail(IPGC_ELIMIT, "rounds did not finish");
+    if (!ws.host_ct->finished) {
+        unsigned aborted = 0;
+        HIP_TRY(hipMemcpy(&aborted, &ws.bar.p->abort.v, sizeof aborted, hipMemcpyDeviceToHost));
+        if (aborted)
+            return fail(IPGC_EHIP, "a grid-barrier wait exceeded %d ms: not every workgroup of the cooperative "
+                        "launch ran (%d workgroups)", P.barrier_ms, grid);
+        return fail(IPGC_ELIMIT, "rounds did not finish");
+    }
     const int32_t rounds = ws.host_ct->rounds;
     if (trace) {
         const int64_t k = std::min<int64_t>(trace->capacity, rounds);
@@ -504,22 +585,22 @@ extern "C" {
 
 int ipgc_color_graph(const int32_t *csr_rowptr, const int32_t *csr_colidx, int64_t n, int64_t m, int mode,
                      int32_t *out_colors, int32_t *out_rounds) {
-    return ipgc::color_impl(csr_rowptr, csr_colidx, n, m, mode, nullptr, nullptr, out_colors, out_rounds, nullptr);
+    IPGC_GUARD(ipgc::color_impl(csr_rowptr, csr_colidx, n, m, mode, nullptr, nullptr, out_colors, out_rounds, nullptr));
 }
 
 int ipgc_color_graph_ex(const int32_t *csr_rowptr, const int32_t *csr_colidx, int64_t n, int64_t m, int mode,
                         const ipgc_options *options, void *stream, int32_t *out_colors, int32_t *out_rounds,
                         ipgc_trace *trace) {
-    return ipgc::color_impl(csr_rowptr, csr_colidx, n, m, mode, options, (hipStream_t)stream, out_colors, out_rounds,
-                            trace);
+    IPGC_GUARD(ipgc::color_impl(csr_rowptr, csr_colidx, n, m, mode, options, (hipStream_t)stream, out_colors,
+                                out_rounds, trace));
 }
 
 int ipgc_color_graphs_batched(int64_t num_graphs, const int64_t *node_off, const int64_t *edge_off,
                               const int32_t *rowptr_packed, const int32_t *colidx_packed, int mode,
                               const ipgc_options *options, void *stream, int32_t *out_colors_packed,
                               int32_t *out_rounds, ipgc_trace *trace) {
-    return ipgc::batch_impl(num_graphs, node_off, edge_off, rowptr_packed, colidx_packed, mode, options,
-                            (hipStream_t)stream, out_colors_packed, out_rounds, trace);
+    IPGC_GUARD(ipgc::batch_impl(num_graphs, node_off, edge_off, rowptr_packed, colidx_packed, mode, options,
+                                (hipStream_t)stream, out_colors_packed, out_rounds, trace));
 }
 
 const char *ipgc_last_error(void) { return ipgc::g_err; }
@@ -528,7 +609,7 @@ const char *ipgc_kernel_name(int kind) { return kind >= 0 && kind < ipgc::kNumKi
 
 const char *ipgc_unit_name(int kind) { return kind >= 0 && kind < ipgc::kNumUnits ? ipgc::kUnitNames[kind] : ""; }
 
-int ipgc_version(void) { return (1 << 16) | 4; }
+int ipgc_version(void) { return (2 << 16) | 0; }
 
 void ipgc_release_workspaces(void) {
     std::lock_guard<std::mutex> lock(ipgc::g_mutex);
@@ -540,6 +621,17 @@ void ipgc_release_workspaces(void) {
     (void)hipSetDevice(cur);
     ipgc::g_ws.clear();
     ipgc::release_bfs_workspaces();
+}
+
+int ipgc_set_allocator(ipgc_alloc_fn alloc, ipgc_free_fn free_fn, void *user) {
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return ipgc::fail(IPGC_EINVAL, "ipgc_set_allocator takes both functions or neither");
+    std::lock_guard<std::mutex> lock(ipgc::g_alloc_mutex);
+    ipgc::g_alloc.alloc = alloc;
+    ipgc::g_alloc.free = free_fn;
+    ipgc::g_alloc.user = alloc ? user : nullptr;
+    ipgc::g_err[0] = 0;
+    return IPGC_OK;
 }
 
 }  // extern "C"

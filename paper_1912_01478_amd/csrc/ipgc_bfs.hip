@@ -45,8 +45,9 @@ struct BfsDev {
     int64_t n;
     int64_t threshold;    // topology-driven level iff |frontier| > threshold
     int32_t cap;
-    int32_t *levels;      // out: non-empty levels
+    int32_t *levels;      // out: non-empty levels (stays -1 if a grid-barrier wait gave up)
     Barrier *bar;
+    uint64_t bar_limit;   // wall-clock ticks a grid-barrier wait may last
 };
 
 // Prefix sums over the grid segments plus the overflow list (grid + 1 parts) in shared memory.
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsDev d) {
     __shared__ int32_t heavy[kHeavyPerBlock];
     __shared__ int s_cnt, s_heavy;
     GridBarrier gb;
-    gb.setup(d.bar);
+    if (!gb.setup(d.bar, d.bar_limit)) return;
     const int64_t nt = (int64_t)gridDim.x * blockDim.x;
     const int lane = lane_id(), w = threadIdx.x / kWave, nwv = blockDim.x / kWave;
     int32_t lvl = 0;
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsDev d) {
             s_heavy = 0;
         }
         __syncthreads();
-        gb.sync();  // every part of the frontier is read before any segment of the next one is written
+        if (!gb.sync()) return;  // every part of the frontier is read before any segment of the next one is written
         for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < items; i0 += nt) {
             const int64_t i = i0 + threadIdx.x;
             int32_t v = -1;
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs(BfsDev d) {
             __syncthreads();
         }
         if (threadIdx.x == 0) d.seg_cnt[dst][blockIdx.x] = min(s_cnt, d.cap);
-        gb.sync();
+        if (!gb.sync()) return;
     }
 }
 
@@ -265,7 +266,7 @@ extern "C" int ipgc_bfs(const int32_t *rowptr, const int32_t *colidx, int64_t n,
                 break;
             }
         }
-        const int32_t zero3[3] = {0, 0, 0}, src32 = (int32_t)source, dist0 = 0;
+        const int32_t zero3[3] = {0, 0, 0}, src32 = (int32_t)source, dist0 = 0, unset = -1;
         std::vector<int32_t> cnt(kMaxRoundBlocks, 0);
         cnt[0] = 1;
         if (hipMemsetAsync(out_dist, 0xff, sizeof(int32_t) * n, s) != hipSuccess ||
@@ -274,6 +275,7 @@ extern "C" int ipgc_bfs(const int32_t *rowptr, const int32_t *colidx, int64_t n,
             hipMemcpyAsync(cnt0.p, cnt.data(), sizeof(int32_t) * kMaxRoundBlocks, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemsetAsync(cnt1.p, 0, sizeof(int32_t) * kMaxRoundBlocks, s) != hipSuccess ||
             hipMemcpyAsync(ovfc.p, zero3, sizeof zero3, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(lv.p, &unset, sizeof(int32_t), hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemsetAsync(bar.p, 0, sizeof(Barrier), s) != hipSuccess) {
             rc = fail(IPGC_EHIP, "BFS set-up failed");
             break;
@@ -294,6 +296,7 @@ extern "C" int ipgc_bfs(const int32_t *rowptr, const int32_t *colidx, int64_t n,
         d.threshold = H;
         d.levels = lv.p;
         d.bar = bar.p;
+        if ((rc = barrier_limit_ticks(dev, P.barrier_ms, &d.bar_limit))) break;
         void *args[] = {&d};
         if (hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_bfs), dim3(grid), dim3(kBlock), args, 0, s) !=
             hipSuccess) {
@@ -304,6 +307,11 @@ extern "C" int ipgc_bfs(const int32_t *rowptr, const int32_t *colidx, int64_t n,
         if (hipMemcpyAsync(&levels, lv.p, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             rc = fail(IPGC_EHIP, "BFS read-back failed");
+            break;
+        }
+        if (levels < 0) {
+            rc = fail(IPGC_EHIP, "a grid-barrier wait exceeded %d ms: not every workgroup of the cooperative launch ran "
+                      "(%d workgroups)", P.barrier_ms, grid);
             break;
         }
         if (trace) {

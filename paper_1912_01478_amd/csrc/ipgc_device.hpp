@@ -115,6 +115,7 @@ struct Barrier {
     Line gen;             // global generation
     Line xgen[kMaxXcc];   // generation released per XCD
     Line setup;           // one-time flat barrier counter
+    Line abort;           // set by a workgroup whose wait exceeded the time limit: everyone leaves
     unsigned xcc_of[kMaxRoundBlocks];  // XCD of every workgroup (for a smaller set of participants)
 };
 
@@ -124,8 +125,8 @@ struct Counters {
     int64_t unit_nodes[4];            // active nodes per class summed over rounds
     int64_t unit_edges[4];            // their degree sums summed over rounds
     int32_t class_n[kNumClasses];     // nodes per class
+    int64_t seg_off[4];               // class regions of the segmented lists
     int32_t static_off[4];            // class regions of the static list
-    int32_t seg_off[4];               // class regions of the segmented lists
     int32_t seg_cap[kNumClasses];     // entries per workgroup segment, per class
     int32_t finished;
     int32_t rounds;
@@ -134,7 +135,7 @@ struct Counters {
     int32_t unsorted;
     int32_t hub_winners;              // hubs committed in the current round
     int32_t prev_discarded;           // the last round kept no worklist (discard mode, stepped launches)
-    int32_t pad;
+    int32_t bad_full;                 // IPGC_VALIDATE_FULL: bit 0 self-loop, bit 1 duplicate, bit 2 no reverse entry
 };
 
 // A committed hub waiting for the push step.
@@ -193,6 +194,7 @@ struct DevT {
     int32_t racy;            // in-place mode: losers uncolor at once, L assigns avoid in-flight tentatives
     int32_t discard;         // topology-driven rounds keep no worklist; it is rebuilt when data rounds start
     int32_t tail_groups;     // workgroups that stay in the round loop for small data-driven rounds (0: all)
+    uint64_t bar_limit;      // wall-clock ticks a grid-barrier wait may last
 
     // global id of a neighbour stored in row entry k of node v
     __device__ __forceinline__ int32_t base(int32_t v) const { return gbase ? gbase[v] : 0; }
@@ -252,26 +254,52 @@ __device__ __forceinline__ unsigned xcc_id() {
 struct GridBarrier {
     Barrier *b;
     unsigned xcc, nxcc, gen;
-    unsigned xs;  // participating workgroups on this workgroup's XCD
+    unsigned xs;      // participating workgroups on this workgroup's XCD
+    uint64_t limit;   // wall-clock ticks any one wait may last
+
+    // True once this wait should end without the barrier: it has lasted longer
+    // than the limit (then every other workgroup is told to leave too), or
+    // another workgroup gave up.
+    __device__ __forceinline__ bool give_up(uint64_t t0) const {
+        if (ld_agent(&b->abort.v)) return true;
+        if (wall_clock64() - t0 > limit) {
+            st_agent(&b->abort.v, 1u);
+            return true;
+        }
+        return false;
+    }
 
     // One-time setup: count the workgroups of every XCD (flat barrier with a
-    // per-workgroup release and acquire; used once per launch).
-    __device__ void setup(Barrier *bar) {
+    // per-workgroup release and acquire; used once per launch).  False if the
+    // wait gave up: the caller leaves the kernel.
+    __device__ bool setup(Barrier *bar, uint64_t lim) {
+        __shared__ int s_ok;
         b = bar;
+        limit = lim;
         xcc = xcc_id();
         if (threadIdx.x == 0) {
             add_agent(&b->xsize[xcc].v, 1u);
             b->xcc_of[blockIdx.x] = xcc;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             add_agent(&b->setup.v, 1u);
-            while (ld_agent(&b->setup.v) < gridDim.x) __builtin_amdgcn_s_sleep(2);
+            const uint64_t t0 = wall_clock64();
+            int ok = 1;
+            while (ld_agent(&b->setup.v) < gridDim.x) {
+                if (give_up(t0)) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_ok = ok;
         }
         __syncthreads();
         nxcc = 0;
         for (int i = 0; i < kMaxXcc; ++i) nxcc += ld_agent(&b->xsize[i].v) > 0;
         xs = ld_agent(&b->xsize[xcc].v);
         gen = 0;
+        return s_ok != 0;
     }
 
     // From now on only workgroups 0 .. g-1 take part (every one of them calls
@@ -288,11 +316,17 @@ struct GridBarrier {
         __syncthreads();
     }
 
-    __device__ void sync() {
+    // False if the wait gave up (the caller leaves the kernel).  A leader that
+    // gives up does not release its XCD, so no workgroup goes on past a barrier
+    // that not every workgroup reached.
+    __device__ bool sync() {
+        __shared__ int s_ok;
         __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have reached the XCD's L2
         __syncthreads();
         if (threadIdx.x == 0) {
             const unsigned g = gen;
+            const uint64_t t0 = wall_clock64();
+            int ok = 1;
             if (add_agent(&b->xcnt[xcc].v, 1u) == xs - 1) {
                 st_agent(&b->xcnt[xcc].v, 0u);
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // write back this XCD's L2
@@ -300,17 +334,33 @@ struct GridBarrier {
                     st_agent(&b->gcnt.v, 0u);
                     st_agent(&b->gen.v, g + 1);
                 } else {
-                    while (ld_agent(&b->gen.v) == g) __builtin_amdgcn_s_sleep(1);
+                    while (ld_agent(&b->gen.v) == g) {
+                        if (give_up(t0)) {
+                            ok = 0;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                st_agent(&b->xgen[xcc].v, g + 1);
+                if (ok) st_agent(&b->xgen[xcc].v, g + 1);
             } else {
-                while (ld_agent(&b->xgen[xcc].v) == g) __builtin_amdgcn_s_sleep(1);
+                while (ld_agent(&b->xgen[xcc].v) == g) {
+                    if (give_up(t0)) {
+                        ok = 0;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
+            s_ok = ok;
         }
         gen += 1;
         __syncthreads();
+        // every thread reads s_ok before it arrives at the next sync, whose write of s_ok
+        // follows that sync's first workgroup barrier
+        return s_ok != 0;
     }
 };
 
@@ -470,7 +520,7 @@ __global__ __launch_bounds__(1024) void k_offsets(D d, int32_t prep_grid) {
         off[0] = 0;
         for (int k = 1; k < kNumClasses; ++k) off[k] = d.block_cnt[k * prep_grid];
         off[kNumClasses] = d.n;
-        int32_t so = 0;
+        int64_t so = 0;
         for (int k = 0; k < kNumClasses; ++k) {
             d.ct->static_off[k] = off[k];
             d.ct->class_n[k] = off[k + 1] - off[k];
@@ -590,6 +640,110 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep_wide(D d) {
     }
     if (__ballot(bad) && lane_id() == 0) d.ct->bad_ids = 1;
     if (__ballot(unsorted) && lane_id() == 0) d.ct->unsorted = 1;
+}
+
+// ============================================================== full validation
+//
+// IPGC_VALIDATE_FULL: the input must be a simple symmetric graph (Section V
+// colors graphs with self-loops and multi-edges removed; the method is defined
+// on undirected graphs).  k_full_sort writes every row, sorted, into a scratch
+// array with the CSR's layout; k_full_check then flags a self-loop, a repeated
+// id in a row, or an entry (v, u) with no reverse entry (u, v), found by binary
+// search in the sorted row of u.  Every entry's reverse present and no
+// repeated entries make the CSR exactly symmetric.
+
+constexpr int kSortBlock = 256;
+constexpr int kSortShared = 4096;  // rows up to this length are sorted in shared memory
+
+enum { kFullSelfLoop = 1, kFullDuplicate = 2, kFullAsymmetric = 4 };
+
+// Sorts a[0, len) ascending with the whole workgroup.  A bitonic network in
+// which every comparator puts the smaller value at the lower position (the
+// first stage of each merge pairs mirrored positions), so positions at or past
+// len act as +infinity: a comparator that reaches one would never swap, and is
+// skipped.  Stages are separated by workgroup barriers; `a` is shared or
+// global memory of this workgroup alone.
+__device__ void workgroup_sort(int32_t *a, int64_t len) {
+    int64_t N = 1;
+    while (N < len) N <<= 1;
+    for (int64_t k = 2; k <= N; k <<= 1) {
+        for (int64_t j = k - 1; j > 0; j = (j == k - 1) ? (k >> 2) : (j >> 1)) {
+            for (int64_t i = threadIdx.x; i < len; i += blockDim.x) {
+                const int64_t q = i ^ j;
+                if (q > i && q < len) {
+                    const int32_t x = a[i], y = a[q];
+                    if (y < x) {
+                        a[i] = y;
+                        a[q] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Every row of nodes [v_lo, v_hi), sorted, into out (same positions as colidx).
+// Nothing is read if *skip is set (a server job whose rows failed their checks).
+template <class D>
+__global__ __launch_bounds__(kSortBlock) void k_full_sort(D d, int64_t v_lo, int64_t v_hi, int32_t *out,
+                                                          const int32_t *skip) {
+    __shared__ int32_t s[kSortShared];
+    if (skip && *skip) return;
+    for (int64_t v = v_lo + blockIdx.x; v < v_hi; v += gridDim.x) {
+        const int64_t b = d.rowptr[v], len = d.rowptr[v + 1] - b;
+        int unsorted = 0;
+        for (int64_t i = threadIdx.x; i < len; i += blockDim.x) {
+            const int32_t x = d.colidx[b + i];
+            out[b + i] = x;
+            if (i + 1 < len && d.colidx[b + i + 1] < x) unsorted = 1;
+        }
+        if (!__syncthreads_or(unsorted)) continue;  // ascending already: the copy stands
+        if (len <= kSortShared) {
+            for (int64_t i = threadIdx.x; i < len; i += blockDim.x) s[i] = out[b + i];
+            __syncthreads();
+            workgroup_sort(s, len);
+            for (int64_t i = threadIdx.x; i < len; i += blockDim.x) out[b + i] = s[i];
+            __syncthreads();
+        } else {
+            workgroup_sort(out + b, len);
+        }
+    }
+}
+
+// Checks of nodes [v_lo, v_hi) on the sorted rows (a wavefront per node); the
+// kFull* bits found are ORed into *flag.  Ids outside the node's graph are left
+// to the range checks (and never used as an index here).
+template <class D>
+__global__ __launch_bounds__(kPrepBlock) void k_full_check(D d, int64_t v_lo, int64_t v_hi, const int32_t *rows,
+                                                           int32_t *flag, const int32_t *skip) {
+    if (skip && *skip) return;
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int lane = lane_id();
+    int bad = 0;
+    for (int64_t v = v_lo + gw; v < v_hi; v += nw) {
+        const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
+        const int64_t lo = d.base((int32_t)v), hi = d.id_end((int32_t)v);
+        const int32_t vl = (int32_t)(v - lo);  // v's id inside its graph, as its neighbours' rows hold it
+        for (int64_t k = b + lane; k < e; k += kWave) {
+            const int32_t ul = rows[k];
+            const int64_t u = (int64_t)ul + lo;
+            if (u < lo || u >= hi) continue;
+            if (u == v) bad |= kFullSelfLoop;
+            if (k + 1 < e && rows[k + 1] == ul) bad |= kFullDuplicate;
+            int64_t a = d.rowptr[u], z = d.rowptr[u + 1];
+            const int64_t end = z;
+            while (a < z) {  // first position of row u holding an id >= vl
+                const int64_t mid = (a + z) >> 1;
+                if (rows[mid] < vl) a = mid + 1;
+                else z = mid;
+            }
+            if (a == end || rows[a] != vl) bad |= kFullAsymmetric;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o);
+    if (bad && lane == 0) atomicOr(flag, bad);
 }
 
 // A packed batch seen as one graph: union row starts (local offsets of graph
@@ -741,7 +895,7 @@ struct OutSegs {
     int32_t *list;     // out list
     int32_t *cnt;      // its segment counts
     int64_t *deg;
-    int cls_off[kNumClasses];
+    int64_t cls_off[kNumClasses];
     int cap[kNumClasses];
 };
 
@@ -1008,7 +1162,7 @@ __device__ bool ring_scan_group(const D &d, int32_t v, int32_t t, int wide, int 
 // varies; the set, and with it every outcome, does not.
 template <class D>
 __device__ void conflict_wide_teams(const D &d, const RoundIn &in, const OutSegs &os, int32_t r, Units &un, int G, int T,
-                                    bool discard, const int32_t (&seg_base)[kNumClasses], int *s_cnt,
+                                    bool discard, const int64_t (&seg_base)[kNumClasses], int *s_cnt,
                                     unsigned long long *s_deg) {
     constexpr int kPass = 4;
     __shared__ int32_t s_kept[kRoundWaves], s_hit[kRoundWaves];
@@ -1126,9 +1280,9 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
     }
     __syncthreads();
     const bool discard = d.discard && in.topo;  // discard mode: a sweep keeps only the losers' count
-    const int32_t seg_base[kNumClasses] = {os.cls_off[kL] + (int32_t)blockIdx.x * os.cap[kL],
-                                           os.cls_off[kW] + (int32_t)blockIdx.x * os.cap[kW],
-                                           os.cls_off[kM] + (int32_t)blockIdx.x * os.cap[kM]};
+    const int64_t seg_base[kNumClasses] = {os.cls_off[kL] + (int64_t)blockIdx.x * os.cap[kL],
+                                           os.cls_off[kW] + (int64_t)blockIdx.x * os.cap[kW],
+                                           os.cls_off[kM] + (int64_t)blockIdx.x * os.cap[kM]};
 
     // classes W and M: a wavefront per node.  W winners write their color into
     // their neighbours' byte maps at once; M winners are recorded for the push step.
@@ -1452,8 +1606,9 @@ template <class D>
 __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int32_t last) {
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
     GridBarrier gb;
-    gb.setup(d.bar);
+    const bool up = gb.setup(d.bar, d.bar_limit);
     Units un;
+    if (!up) last = first - 1;  // a wait gave up: leave at once (the host reports it)
     int32_t r = first;
     int G = gridDim.x;        // workgroups in the round loop
     int writers = gridDim.x;  // workgroups that wrote the list this round reads
@@ -1463,7 +1618,7 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
         RoundIn in = round_view(d, r, pre);
         if (discarded && !in.topo && in.total > 0) {
             rebuild_step(d, r & 1, G);
-            gb.sync();
+            if (!gb.sync()) break;
             writers = G;
             load_segments(d, r & 1, pre, writers);
             in = round_view(d, r, pre);
@@ -1480,12 +1635,12 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
         tick(d, 3 * (int64_t)(r - 1));
         if (r > 1) {  // round 1's tentative colors (all 1) were set at init
             assign_step(d, in, un, G);
-            gb.sync();
+            if (!gb.sync()) break;
         }
         tick(d, 3 * (int64_t)(r - 1) + 1);
         conflict_step(d, in, out_segs(d, r), r, un, G);
         writers = G;
-        gb.sync();
+        if (!gb.sync()) break;
         tick(d, 3 * (int64_t)(r - 1) + 2);
         // every workgroup reads the count here (one load, shared); it is cleared only after the next barrier
         __shared__ int32_t s_nwon;
@@ -1494,7 +1649,7 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
         const int32_t nwon = s_nwon;
         if (nwon > 0) {
             hub_push_step(d, nwon, un, G);
-            gb.sync();
+            if (!gb.sync()) break;
             if (blockIdx.x == 0 && threadIdx.x == 0) d.ct->hub_winners = 0;
         }
     }

@@ -24,6 +24,7 @@
 // Between steps every byte of state stays on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstring>
 #include <deque>
@@ -298,7 +299,9 @@ struct Server {
     DBuf<uint8_t> F;
     DBuf<HubRec> hub_won;
     DBuf<Barrier> bar;
+    DBuf<Counters> ctb;
     Counters *ct = nullptr, *host_ct = nullptr;
+    uint64_t bar_limit = 0;
 
     RangeAlloc nodes, edges, fbytes;
     std::vector<int32_t> free_slots;
@@ -315,6 +318,9 @@ struct Server {
 
     int create(const ipgc_server_config &cfg);
     void destroy();
+    int cancel(int64_t job_id);
+    int wait(int64_t job_id, ipgc_job_result *out);
+    bool pending(int64_t job_id) const;
     SDev dev_view(int64_t nhigh, int64_t threshold);
     int reserve_and_upload();
     int admit_staged();
@@ -385,15 +391,17 @@ int Server::create(const ipgc_server_config &cfg) {
     TRY(gleft.reserve(max_jobs));
     TRY(gerr.reserve(max_jobs));
     TRY(bar.reserve(1));
-    HIP_TRY(hipMalloc(&ct, sizeof(Counters)));
+    TRY(ctb.reserve(1));
+    ct = ctb.p;
     HIP_TRY(hipHostMalloc(&host_ct, sizeof(Counters), hipHostMallocDefault));
+    TRY(barrier_limit_ticks(dev, P.barrier_ms, &bar_limit));
 
     HIP_TRY(hipMemsetAsync(cls.p, 0xff, ncap, s));  // every slot kNoNode
     HIP_TRY(hipMemsetAsync(gleft.p, 0, sizeof(int32_t) * max_jobs, s));
     HIP_TRY(hipMemsetAsync(units.p, 0, sizeof(int64_t) * kNumUnits * kMaxRoundBlocks, s));
     HIP_TRY(hipMemsetAsync(F.p, 0, fcap + 2 * kFPad, s));
     Counters h{};
-    for (int k = 0; k <= kNumClasses; ++k) h.seg_off[k] = k * grid * seg_cap;
+    for (int k = 0; k <= kNumClasses; ++k) h.seg_off[k] = (int64_t)k * grid * seg_cap;
     for (int k = 0; k < kNumClasses; ++k) h.seg_cap[k] = seg_cap;
     *host_ct = h;
     HIP_TRY(hipMemcpyAsync(ct, host_ct, sizeof(Counters), hipMemcpyHostToDevice, s));
@@ -420,8 +428,7 @@ void Server::destroy() {
     colidx.release(); gbase.release(); gidx.release(); c.release(); lower.release(); lstart.release();
     llen.release(); static_list.release(); seg0.release(); seg1.release(); seg_cnt.release();
     block_cnt.release(); stage.release(); grounds.release(); gleft.release(); gerr.release(); cls.release();
-    F.release(); mask.release(); pend.release(); hub_won.release(); bar.release();
-    if (ct) (void)hipFree(ct);
+    F.release(); mask.release(); pend.release(); hub_won.release(); bar.release(); ctb.release();
     if (host_ct) (void)hipHostFree(host_ct);
     if (s) (void)hipStreamDestroy(s);
     if (cs) (void)hipStreamDestroy(cs);
@@ -479,6 +486,7 @@ SDev Server::dev_view(int64_t nhigh, int64_t threshold) {
     d.racy = P.racy ? 1 : 0;
     d.tail_groups = P.tail_groups;
     d.discard = P.mode == IPGC_MODE_REBUILD ? 1 : 0;
+    d.bar_limit = bar_limit;
     return d;
 }
 
@@ -577,6 +585,12 @@ int Server::admit_staged() {
                                            lstart.p, llen.p, gend.p, gfshift.p, gleft.p, grounds.p, gerr.p);
         SDev d = dev_view(nodes.high(), 0);
         const int pblocks = (int)std::min<int64_t>(8192, (j.n + 3) / 4);
+        if (P.full) {
+            // sorted rows in the job's ring slots (the rings are built over them next), then the checks
+            k_full_sort<<<(int)std::min<int64_t>(j.n, 65536), kSortBlock, 0, s>>>(d, v0, v0 + j.n, lower.p, gerr.p + slot);
+            k_full_check<<<std::max(1, pblocks), kPrepBlock, 0, s>>>(d, v0, v0 + j.n, lower.p, gerr.p + slot,
+                                                                    gerr.p + slot);
+        }
         k_srv_prep<<<std::max(1, pblocks), 256, 0, s>>>(d, (int32_t)v0, j.n, slot, gerr.p);
         k_srv_reject<<<blocks, 256, 0, s>>>(cls.p, (int32_t)v0, j.n + 1, slot, gerr.p);
         HIP_TRY(hipGetLastError());
@@ -626,6 +640,13 @@ int Server::step() {
     // while the rounds run: upload the next jobs that fit now
     TRY(reserve_and_upload());
     HIP_TRY(hipStreamSynchronize(s));
+    if (!host_ct->finished) {
+        unsigned aborted = 0;
+        HIP_TRY(hipMemcpy(&aborted, &bar.p->abort.v, sizeof aborted, hipMemcpyDeviceToHost));
+        if (aborted)
+            return fail(IPGC_EHIP, "a grid-barrier wait exceeded %d ms: not every workgroup of the cooperative launch "
+                        "ran (%d workgroups)", P.barrier_ms, grid);
+    }
     const int32_t ran_to = host_ct->finished ? host_ct->rounds : last;
     st.rounds += ran_to - first + 1;
     st.steps += 1;
@@ -641,6 +662,72 @@ int Server::step() {
     return retire(finished, IPGC_OK);
 }
 
+// A job that has not finished: queued, staged (upload issued) or resident.
+bool Server::pending(int64_t job_id) const {
+    for (const Job &j : queue)
+        if (j.id == job_id) return true;
+    for (const Job &j : slot_job)
+        if (j.slot >= 0 && j.id == job_id) return true;
+    return false;
+}
+
+int Server::cancel(int64_t job_id) {
+    for (auto it = queue.begin(); it != queue.end(); ++it) {
+        if (it->id != job_id) continue;
+        queue.erase(it);
+        st.queued = (int64_t)queue.size();
+        done.push_back(ipgc_job_result{job_id, IPGC_ECANCELED, -1});
+        st.cancelled += 1;
+        st.completed += 1;
+        return IPGC_OK;
+    }
+    int32_t slot = -1;
+    for (const Job &j : slot_job)
+        if (j.slot >= 0 && j.id == job_id) slot = j.slot;
+    if (slot < 0) {
+        for (const ipgc_job_result &r : done)
+            if (r.job_id == job_id) return fail(IPGC_EINVAL, "job %lld has already finished", (long long)job_id);
+        return fail(IPGC_EINVAL, "no job %lld is queued or resident", (long long)job_id);
+    }
+    Job &j = slot_job[slot];
+    if (!j.admitted) {
+        // its upload reads the caller's arrays: let it end before the job is reported
+        HIP_TRY(hipStreamSynchronize(cs));
+        staged.erase(std::find(staged.begin(), staged.end(), slot));
+    } else {
+        // the job's node slots leave the union; the next step rebuilds the worklist and static lists without them
+        k_srv_retire<<<(int)std::min<int64_t>(1024, (j.n + 1 + 255) / 256), 256, 0, s>>>(cls.p, (int32_t)j.v0, j.n + 1);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(s));
+        static_dirty = true;
+    }
+    nodes.release(j.v0, j.n + 1);
+    edges.release(j.e0, j.m);
+    fbytes.release(j.f0, j.m + j.n + 8);
+    done.push_back(ipgc_job_result{job_id, IPGC_ECANCELED, -1});
+    st.resident -= 1;
+    st.resident_nodes -= j.n;
+    st.resident_edges -= j.m;
+    st.cancelled += 1;
+    st.completed += 1;
+    free_slots.push_back(slot);
+    j = Job();
+    return IPGC_OK;
+}
+
+int Server::wait(int64_t job_id, ipgc_job_result *out) {
+    for (;;) {
+        for (auto it = done.begin(); it != done.end(); ++it) {
+            if (it->job_id != job_id) continue;
+            *out = *it;
+            done.erase(it);
+            return IPGC_OK;
+        }
+        if (!pending(job_id)) return fail(IPGC_EINVAL, "no job %lld is pending or unreported", (long long)job_id);
+        TRY(step());
+    }
+}
+
 }  // namespace srv
 }  // namespace ipgc
 
@@ -651,6 +738,7 @@ struct ipgc_server {
 extern "C" {
 
 int ipgc_server_create(const ipgc_server_config *config, ipgc_server **out) {
+    IPGC_GUARD(([&]() -> int {
     using namespace ipgc;
     using namespace ipgc::srv;
     if (!config || !out) return fail(IPGC_EINVAL, "null pointer");
@@ -668,10 +756,12 @@ int ipgc_server_create(const ipgc_server_config *config, ipgc_server **out) {
     *out = sv;
     g_err[0] = 0;
     return IPGC_OK;
+    })());
 }
 
 int ipgc_server_submit(ipgc_server *server, const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t m,
                        int32_t *out_colors, int64_t *job_id) {
+    IPGC_GUARD(([&]() -> int {
     using namespace ipgc;
     using namespace ipgc::srv;
     if (!server || !job_id) return fail(IPGC_EINVAL, "null pointer");
@@ -699,6 +789,7 @@ int ipgc_server_submit(ipgc_server *server, const int32_t *rowptr, const int32_t
     }
     g_err[0] = 0;
     return IPGC_OK;
+    })());
 }
 
 int ipgc_server_step(ipgc_server *server) {
@@ -708,7 +799,46 @@ int ipgc_server_step(ipgc_server *server) {
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
     if (cur != server->impl.dev) HIP_TRY(hipSetDevice(server->impl.dev));
-    const int rc = server->impl.step();
+    int rc;
+    try {
+        rc = server->impl.step();
+    } catch (const std::bad_alloc &) {
+        rc = fail(IPGC_ENOMEM, "host memory allocation failed");
+    }
+    if (cur != server->impl.dev) (void)hipSetDevice(cur);
+    if (rc == IPGC_OK) g_err[0] = 0;
+    return rc;
+}
+
+int ipgc_server_wait(ipgc_server *server, int64_t job_id, ipgc_job_result *result) {
+    using namespace ipgc;
+    if (!server || !result) return fail(IPGC_EINVAL, "null pointer");
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != server->impl.dev) HIP_TRY(hipSetDevice(server->impl.dev));
+    int rc;
+    try {
+        rc = server->impl.wait(job_id, result);
+    } catch (const std::bad_alloc &) {
+        rc = fail(IPGC_ENOMEM, "host memory allocation failed");
+    }
+    if (cur != server->impl.dev) (void)hipSetDevice(cur);
+    if (rc == IPGC_OK) g_err[0] = 0;
+    return rc;
+}
+
+int ipgc_server_cancel(ipgc_server *server, int64_t job_id) {
+    using namespace ipgc;
+    if (!server) return fail(IPGC_EINVAL, "null server");
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != server->impl.dev) HIP_TRY(hipSetDevice(server->impl.dev));
+    int rc;
+    try {
+        rc = server->impl.cancel(job_id);
+    } catch (const std::bad_alloc &) {
+        rc = fail(IPGC_ENOMEM, "host memory allocation failed");
+    }
     if (cur != server->impl.dev) (void)hipSetDevice(cur);
     if (rc == IPGC_OK) g_err[0] = 0;
     return rc;

@@ -40,14 +40,56 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_version(lib):
-    assert lib.ipgc_version() >> 16 == 1
+    assert lib.ipgc_version() >> 16 == 2
 
 
-def test_struct_layouts():
+# Structs the binding mirrors, with the fields whose offsets are compared against the header.
+MIRRORS = {
+    "ipgc_options": ("Options", ["threshold", "light_max_degree", "hub_min_degree", "validate", "flags", "profile",
+                                 "workgroups", "tail_workgroups", "barrier_timeout_ms", "reserved"]),
+    "ipgc_trace": ("Trace", ["capacity", "wl_size", "wl_degree", "topology", "recorded"]),
+    "ipgc_profile": ("Profile", ["mask", "kinds", "ms", "launches", "unit_kinds", "reserved", "units", "phase_ticks",
+                                 "phase_capacity", "phase_recorded", "tick_khz"]),
+    "ipgc_server_config": ("ServerConfig", ["node_capacity", "edge_capacity", "max_jobs", "rounds_per_step", "mode",
+                                            "reserved", "options"]),
+    "ipgc_job_result": ("JobResult", ["job_id", "status", "rounds"]),
+    "ipgc_server_stats": ("ServerStats", ["steps", "cancelled", "rounds", "submitted", "admitted", "completed",
+                                          "resident", "queued", "resident_nodes", "resident_edges", "peak_resident",
+                                          "arena_bytes", "units"]),
+}
+
+
+@pytest.fixture(scope="module")
+def c_layouts(tmp_path_factory):
+    """sizeof and offsetof of every mirrored struct, as a C compiler lays out include/ipgc.h."""
+    import subprocess
+    d = tmp_path_factory.mktemp("abi")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", "#include \"ipgc.h\"", "int main(void) {"]
+    for cname, (_, fields) in MIRRORS.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f in fields:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = d / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = d / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = {}
+    for line in subprocess.check_output([str(exe)]).decode().splitlines():
+        a, b, c = line.split()
+        out[(a, b)] = int(c)
+    return out
+
+
+@pytest.mark.parametrize("cname", sorted(MIRRORS))
+def test_struct_layouts_match_header(c_layouts, cname):
     import paper_1912_01478_amd as pkg
-    assert ctypes.sizeof(pkg.Options) == 40
-    assert ctypes.sizeof(pkg.Trace) == 40
-    assert ctypes.sizeof(pkg.Profile) == 8 + 8 * 16 * 2 + 8 + 8 * 16 + 32
+    pyname, fields = MIRRORS[cname]
+    cls = getattr(pkg, pyname)
+    assert ctypes.sizeof(cls) == c_layouts[(cname, "size")]
+    assert [f for f, _ in cls._fields_] == fields
+    for f in fields:
+        assert getattr(cls, f).offset == c_layouts[(cname, f)], (cname, f)
 
 
 def test_kernel_names(lib):
@@ -82,10 +124,3 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(pkg, "_lib", None)
     with pytest.raises(ImportError):
         pkg.library()
-
-
-def test_server_struct_layouts():
-    import paper_1912_01478_amd as pkg
-    assert ctypes.sizeof(pkg.ServerConfig) == 8 + 8 + 4 * 4 + 40
-    assert ctypes.sizeof(pkg.JobResult) == 16
-    assert ctypes.sizeof(pkg.ServerStats) == 11 * 8 + 16 * 8

@@ -267,6 +267,7 @@ def _sha(a):
 def test_full_size_against_oracle_digest(cfg):
     """Full-size workloads (G(10 000, 8); R-MAT scale 22 ef 16; road kNN on 24M points) against
     digests of the oracle's colors and worklist trace written by golden/make_oracle_digests.py."""
+    from paper_1912_01478_amd import autotune as at
     d = _digests()[str(cfg)]
     g = gg.config_graph(cfg)
     assert g.digest() == d["graph_sha256"], "generator output changed"
@@ -276,3 +277,11 @@ def test_full_size_against_oracle_digest(cfg):
         assert _sha(wl.astype(np.int32)) == d["wl_sizes_sha256"]
         assert _sha(col) == d["colors_sha256"]
     P.check_coloring(g.rowptr, g.colidx, col, rounds)
+    # the options bench.py times for this workload: the tuning table's choice for its class
+    choice = at.TuneTable.load(at.DEFAULT_TABLE).lookup(at.graph_features(g.rowptr))
+    if choice is not None:
+        kw = at.call_kwargs(choice, g.n)
+        col, rounds, wl, _ = gpu(g, **kw)
+        assert rounds == d["rounds"]
+        assert _sha(wl.astype(np.int32)) == d["wl_sizes_sha256"]
+        assert _sha(col) == d["colors_sha256"]
