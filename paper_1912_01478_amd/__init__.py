@@ -35,7 +35,8 @@ STATUS = {0: "IPGC_OK", -1: "IPGC_EINVAL", -2: "IPGC_ETOOBIG", -3: "IPGC_EBADCSR
           -5: "IPGC_EHIP", -6: "IPGC_ELIMIT", -7: "IPGC_ECANCELED"}
 
 # Every symbol the header declares; the tests check that the library exports all of them.
-EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_color_graphs_batched", "ipgc_last_error",
+EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_color_graphs_batched",
+           "ipgc_last_error",
            "ipgc_kernel_name", "ipgc_unit_name", "ipgc_version", "ipgc_release_workspaces", "ipgc_server_create",
            "ipgc_server_submit", "ipgc_server_step", "ipgc_server_poll", "ipgc_server_stats_get",
            "ipgc_server_destroy", "ipgc_server_wait", "ipgc_server_cancel", "ipgc_set_allocator",

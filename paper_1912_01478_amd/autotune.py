@@ -19,11 +19,17 @@ import os
 from dataclasses import dataclass, field
 
 # Candidate values per knob, in the order the search visits them.  0 means the library default.
+# Workgroup counts stop at 256: the round kernels run one 1024-thread workgroup per CU, so larger
+# counts are clamped to the 256 co-resident workgroups of an MI355X and would re-time the same
+# launch.  The hybrid thresholds bracket the crossover the worklist push micro-benchmark measures
+# on this device with segmented pushes (iterating the worklist wins below about 20% of the nodes
+# active), beside the paper's 60% ("hybrid") and the smaller values that won on batches.
 KNOBS = {
-    "workgroups": [0, 64, 128, 256, 384, 512],
+    "workgroups": [0, 64, 128, 256],
     "light_max_degree": [0, 8, 16],
     "hub_min_degree": [0, 256, 4096, 16384],
-    "schedule": ["hybrid", "data", "hybrid_h2", "hybrid_h10", "topology", "rebuild"],
+    "schedule": ["hybrid", "data", "hybrid_h40", "hybrid_h30", "hybrid_h20", "hybrid_h10", "hybrid_h2", "topology",
+                 "rebuild"],
     "light": ["auto", "pull", "push"],
     "tail_workgroups": [0, -1, 32, 64, 128],
 }

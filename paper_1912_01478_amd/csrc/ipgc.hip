@@ -26,6 +26,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "ipgc.h"
@@ -103,36 +104,71 @@ struct Workspace {
     DBuf<Counters> ctb;
     DBuf<int32_t> sorted_rows;  // IPGC_VALIDATE_FULL: every row sorted (m entries)
     Counters *ct = nullptr;       // ctb.p
-    Counters *host_ct = nullptr;  // pinned
+    Counters *host_ct = nullptr;  // pinned (or &host_local for a carved workspace)
+    Counters host_local;
+    bool borrowed = false;        // carved from static scratch: nothing here is owned
     std::vector<hipEvent_t> events;
     int coop_blocks = -1;  // co-resident round workgroups on this device (0: no cooperative launch)
 
-    int reserve(int64_t n, int64_t m, int grid, int prep_grid) {
-        if (!ct) {
-            TRY(ctb.reserve(1));
-            ct = ctb.p;
-        }
-        if (!host_ct) HIP_TRY(hipHostMalloc(&host_ct, sizeof(Counters), hipHostMallocDefault));
+    // Every buffer one call of the single-graph or batched path needs, with its entry count, in
+    // one fixed order (the batched path adds its union arrays itself).  At most m / (hub_min + 1)
+    // nodes have a degree above hub_min, so no more hubs can commit in one round.
+    template <class Fn>
+    int plan(int64_t n, int64_t m, int grid, int prep_grid, int hub_min, bool full, Fn &&f) {
         const int64_t seg = n + (int64_t)kNumClasses * grid * (kRoundBlock + 1);
-        TRY(static_list.reserve(n));
-        TRY(seg_list0.reserve(seg));
-        TRY(seg_list1.reserve(seg));
-        TRY(seg_cnt.reserve(2 * kNumClasses * (int64_t)kMaxRoundBlocks));
-        TRY(seg_deg.reserve(2 * kNumClasses * (int64_t)kMaxRoundBlocks));
-        TRY(hub_won.reserve(n));
-        TRY(block_cnt.reserve((int64_t)kNumClasses * prep_grid));
-        TRY(block_deg.reserve((int64_t)kNumClasses * prep_grid));
-        TRY(units.reserve((int64_t)kNumUnits * kMaxRoundBlocks));
-        TRY(trace.reserve(n));
-        TRY(trace_deg.reserve(n));
-        TRY(cls.reserve(n));
-        TRY(F.reserve(m + n + 64));
-        TRY(mask.reserve(n));
-        TRY(pend.reserve(n));
-        TRY(lower.reserve(m));
-        TRY(lstart.reserve(n));
-        TRY(llen.reserve(n));
-        TRY(bar.reserve(1));
+        TRY(f(ctb, 1));
+        TRY(f(bar, 1));
+        TRY(f(static_list, n));
+        TRY(f(seg_list0, seg));
+        TRY(f(seg_list1, seg));
+        TRY(f(seg_cnt, 2 * kNumClasses * (int64_t)kMaxRoundBlocks));
+        TRY(f(seg_deg, 2 * kNumClasses * (int64_t)kMaxRoundBlocks));
+        TRY(f(hub_won, std::min<int64_t>(n, m / ((int64_t)hub_min + 1) + 1)));
+        TRY(f(block_cnt, (int64_t)kNumClasses * prep_grid));
+        TRY(f(block_deg, (int64_t)kNumClasses * prep_grid));
+        TRY(f(units, (int64_t)kNumUnits * kMaxRoundBlocks));
+        TRY(f(trace, n));
+        TRY(f(trace_deg, n));
+        TRY(f(cls, n));
+        TRY(f(F, m + n + 64));
+        TRY(f(mask, n));
+        TRY(f(pend, n));
+        TRY(f(lower, std::max<int64_t>(m, 1)));
+        TRY(f(lstart, n));
+        TRY(f(llen, n));
+        if (full) TRY(f(sorted_rows, std::max<int64_t>(m, 1)));
+        return IPGC_OK;
+    }
+
+    int reserve(int64_t n, int64_t m, int grid, int prep_grid, int hub_min, bool full) {
+        TRY(plan(n, m, grid, prep_grid, hub_min, full, [](auto &b, int64_t c) { return b.reserve(c); }));
+        ct = ctb.p;
+        if (!host_ct) HIP_TRY(hipHostMalloc(&host_ct, sizeof(Counters), hipHostMallocDefault));
+        return IPGC_OK;
+    }
+
+    // Points every buffer of the plan into [base, base + size), 256-byte aligned pieces in plan
+    // order, without allocating: the buffers are borrowed, and the counters are read back into
+    // host_local.  *used receives the bytes the plan needs; IPGC_ETOOBIG if that exceeds size.
+    int carve(unsigned char *base, size_t size, int64_t n, int64_t m, int grid, int prep_grid, int hub_min, bool full,
+              size_t *used) {
+        size_t off = 0;
+        TRY(plan(n, m, grid, prep_grid, hub_min, full, [&](auto &b, int64_t c) {
+            using T = std::remove_reference_t<decltype(*b.p)>;
+            off = (off + 255) & ~(size_t)255;
+            const size_t bytes = sizeof(T) * (size_t)c;
+            if (off + bytes <= size) b.lend(reinterpret_cast<T *>(base + off), c);
+            else b.release();
+            off += bytes;
+            return IPGC_OK;
+        }));
+        *used = off;
+        if (off > size)
+            return fail(IPGC_ETOOBIG, "this graph needs %llu bytes of scratch; the static scratch holds %llu",
+                        (unsigned long long)off, (unsigned long long)size);
+        ct = ctb.p;
+        host_ct = &host_local;
+        borrowed = true;
         return IPGC_OK;
     }
 
@@ -142,7 +178,7 @@ struct Workspace {
         seg_deg.release(); block_deg.release(); units.release(); trace_deg.release(); cls.release();
         F.release(); mask.release(); pend.release(); ticks.release(); bar.release(); growptr.release(); node_off.release(); edge_off.release();
         gbase.release(); gidx.release(); grounds.release(); ctb.release(); sorted_rows.release();
-        if (host_ct) (void)hipHostFree(host_ct);
+        if (host_ct && !borrowed) (void)hipHostFree(host_ct);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         *this = Workspace();
     }
@@ -298,13 +334,19 @@ int round_grid(Workspace &ws, int dev, const Params &P, int64_t n, int *grid, in
     return IPGC_OK;
 }
 
+// Preparation kernels: workgroup b covers nodes [b * span, (b + 1) * span).
+void prep_layout(int64_t n, int64_t *span, int *prep_grid) {
+    *span = std::max<int64_t>(kPrepSpanMin, (n + kMaxPrepBlocks - 1) / kMaxPrepBlocks);
+    *prep_grid = (int)((n + *span - 1) / *span);
+}
+
 // IPGC_VALIDATE_FULL on a graph whose row pointers and ids have passed their
 // checks: sorted copies of the rows in the workspace, then self-loops,
 // repeated ids and missing reverse entries.
 template <typename Off>
 int check_full(Workspace &ws, hipStream_t s, const DevT<Off> &d, int64_t n, int64_t m) {
-    TRY(ws.sorted_rows.reserve(std::max<int64_t>(m, 1)));
-    HIP_TRY(hipMemsetAsync(&ws.ct->bad_full, 0, sizeof(int32_t), s));
+    TRY(ws.sorted_rows.reserve(std::max<int64_t>(m, 1)));  // in the plan when full validation is on
+    TRY(clear(&ws.ct->bad_full, sizeof(int32_t), s));
     const int sort_grid = (int)std::min<int64_t>(n, 65536);
     k_full_sort<<<sort_grid, kSortBlock, 0, s>>>(d, 0, n, ws.sorted_rows.p, nullptr);
     k_full_check<<<(int)std::min<int64_t>(16384, (n + 3) / 4), kPrepBlock, 0, s>>>(d, 0, n, ws.sorted_rows.p,
@@ -319,9 +361,10 @@ int check_full(Workspace &ws, hipStream_t s, const DevT<Off> &d, int64_t n, int6
 template <typename Off>
 int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int64_t n, int64_t m, int grid,
         int coop, int32_t *out_rounds, ipgc_trace *trace) {
-    const int64_t span = std::max<int64_t>(kPrepSpanMin, (n + kMaxPrepBlocks - 1) / kMaxPrepBlocks);
-    const int prep_grid = (int)((n + span - 1) / span);
-    TRY(ws.reserve(n, m, grid, prep_grid));
+    int64_t span = 0;
+    int prep_grid = 0;
+    prep_layout(n, &span, &prep_grid);
+    TRY(ws.reserve(n, m, grid, prep_grid, P.hub_min, P.full));
     ipgc_profile *prof = P.prof;
     Profiler pf{ws, s, prof ? prof->mask : 0u, {}, 0};
 
@@ -365,14 +408,14 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
     TRY(barrier_limit_ticks(dev, P.barrier_ms, &d.bar_limit));
     if (prof && prof->phase_ticks && prof->phase_capacity > 0) {
         TRY(ws.ticks.reserve(prof->phase_capacity));
-        HIP_TRY(hipMemsetAsync(ws.ticks.p, 0, sizeof(uint64_t) * prof->phase_capacity, s));
+        TRY(clear(ws.ticks.p, sizeof(uint64_t) * prof->phase_capacity, s));
         d.ticks = ws.ticks.p;
         d.tick_cap = prof->phase_capacity;
     }
 
-    HIP_TRY(hipMemsetAsync(ws.bar.p, 0, sizeof(Barrier), s));
-    HIP_TRY(hipMemsetAsync(ws.units.p, 0, sizeof(int64_t) * kNumUnits * grid, s));
-    HIP_TRY(hipMemsetAsync(ws.F.p, 0, (size_t)(m + n + 64), s));  // every byte map starts empty
+    TRY(clear(ws.bar.p, sizeof(Barrier), s));
+    TRY(clear(ws.units.p, sizeof(int64_t) * kNumUnits * grid, s));
+    TRY(clear(ws.F.p, (size_t)(m + n + 64), s));  // every byte map starts empty
     TRY(pf.begin(kKindInit));
     k_init<<<prep_grid, kPrepBlock, 0, s>>>(d, ws.cls.p, (int32_t)span);
     k_offsets<<<1, 1024, 0, s>>>(d, prep_grid);
@@ -495,7 +538,7 @@ int color_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t 
     HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(g_mutex);
     Workspace &ws = workspace(dev);
-    if (!ws.ct) TRY(ws.reserve(0, 0, 1, 1));
+    if (!ws.ct) TRY(ws.reserve(0, 0, 1, 1, kDefaultHubMin, false));
 
     // rowptr[0] == 0 and rowptr[n] == m.
     int32_t ends[2];
@@ -511,7 +554,7 @@ int color_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t 
     d.rowptr = rowptr;
     d.colidx = colidx;
     d.c = out_colors;
-    HIP_TRY(hipMemsetAsync(ws.ct, 0, sizeof(Counters), s));
+    TRY(clear(ws.ct, sizeof(Counters), s));
     TRY(run(ws, dev, s, P, d, n, m, grid, coop, out_rounds, trace));
     g_err[0] = 0;
     return IPGC_OK;
@@ -545,7 +588,7 @@ int batch_impl(int64_t graphs, const int64_t *node_off, const int64_t *edge_off,
     HIP_TRY(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(g_mutex);
     Workspace &ws = workspace(dev);
-    if (!ws.ct) TRY(ws.reserve(0, 0, 1, 1));
+    if (!ws.ct) TRY(ws.reserve(0, 0, 1, 1, kDefaultHubMin, false));
     TRY(ws.growptr.reserve(n + 1));
     TRY(ws.gbase.reserve(n));
     TRY(ws.gidx.reserve(n));
@@ -554,8 +597,8 @@ int batch_impl(int64_t graphs, const int64_t *node_off, const int64_t *edge_off,
     TRY(ws.edge_off.reserve(graphs + 1));
     HIP_TRY(hipMemcpyAsync(ws.node_off.p, node_off, sizeof(int64_t) * (graphs + 1), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(ws.edge_off.p, edge_off, sizeof(int64_t) * (graphs + 1), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemsetAsync(ws.grounds.p, 0, sizeof(int32_t) * graphs, s));
-    HIP_TRY(hipMemsetAsync(ws.ct, 0, sizeof(Counters), s));
+    TRY(clear(ws.grounds.p, sizeof(int32_t) * graphs, s));
+    TRY(clear(ws.ct, sizeof(Counters), s));
     k_batch_union<<<(int)std::min<int64_t>(graphs, 16384), kPrepBlock, 0, s>>>(
         ws.node_off.p, ws.edge_off.p, rowptr_packed, graphs, ws.growptr.p, ws.gbase.p, ws.gidx.p, ws.ct);
     HIP_TRY(hipGetLastError());

@@ -364,6 +364,19 @@ struct GridBarrier {
     }
 };
 
+// Zero fill of bytes [p, p + bytes): single bytes up to the first 16-byte
+// boundary, 16-byte stores, then the tail.  Used instead of hipMemsetAsync
+// for counters, barriers and scratch memory.
+static __global__ __launch_bounds__(256) void k_zero(unsigned char *p, uint64_t bytes) {
+    const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t head = std::min<uint64_t>(bytes, (16 - ((uintptr_t)p & 15)) & 15);
+    const uint64_t n16 = (bytes - head) / 16;
+    if (gt < head) p[gt] = 0;
+    uint4 *q = reinterpret_cast<uint4 *>(p + head);
+    for (uint64_t i = gt; i < n16; i += nt) q[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (uint64_t i = head + 16 * n16 + gt; i < bytes; i += nt) p[i] = 0;
+}
+
 // ============================================================== preparation
 
 // Block-wide exclusive scan of one int per thread (any block size <= 1024).

@@ -81,17 +81,32 @@ inline int grow(T **p, int64_t *cap, AllocOwner *owner, int64_t want) {
     return IPGC_OK;
 }
 
-// A device buffer that only grows (its contents are not kept when it does).
+// A device buffer that only grows (its contents are not kept when it does), or
+// a borrowed piece of memory the library does not own (never grown or freed).
 template <typename T>
 struct DBuf {
     T *p = nullptr;
     int64_t cap = 0;
     AllocOwner owner;
-    int reserve(int64_t n) { return grow(&p, &cap, &owner, n); }
+    bool borrowed = false;
+    int reserve(int64_t n) {
+        if (borrowed) {
+            if (n <= cap) return IPGC_OK;
+            return fail(IPGC_ETOOBIG, "a borrowed buffer of %lld entries cannot hold %lld", (long long)cap, (long long)n);
+        }
+        return grow(&p, &cap, &owner, n);
+    }
+    void lend(T *q, int64_t n) {
+        release();
+        p = q;
+        cap = n;
+        borrowed = true;
+    }
     void release() {
-        if (p) dev_free(p, sizeof(T) * (size_t)cap, owner);
+        if (p && !borrowed) dev_free(p, sizeof(T) * (size_t)cap, owner);
         p = nullptr;
         cap = 0;
+        borrowed = false;
     }
 };
 
@@ -124,5 +139,14 @@ int barrier_limit_ticks(int dev, int barrier_ms, uint64_t *ticks);
 
 // IPGC_OK, or IPGC_EBADCSR with a message for the kFull* bits of a full check.
 int full_check_verdict(int bits);
+
+// Zeroes `bytes` device bytes at p on stream s with a fill kernel (no memset node).
+inline int clear(void *p, size_t bytes, hipStream_t s) {
+    if (!bytes) return IPGC_OK;
+    const int blocks = (int)std::min<uint64_t>(4096, (bytes / 16 + 255) / 256 + 1);
+    k_zero<<<blocks, 256, 0, s>>>(static_cast<unsigned char *>(p), (uint64_t)bytes);
+    HIP_TRY(hipGetLastError());
+    return IPGC_OK;
+}
 
 }  // namespace ipgc

@@ -55,10 +55,11 @@ def test_table_roundtrip_and_nearest(tmp_path):
 
 def test_search_finds_the_cheapest_point():
     """Coordinate descent with a separable synthetic cost reaches its minimum."""
-    cost = {"workgroups": {0: 5, 64: 3, 128: 1, 256: 2, 384: 4, 512: 6},
+    cost = {"workgroups": {0: 5, 64: 3, 128: 1, 256: 2},
             "light_max_degree": {0: 1, 8: 3, 16: 2},
             "hub_min_degree": {0: 2, 256: 1, 4096: 3, 16384: 4},
-            "schedule": {"hybrid": 2, "data": 1, "hybrid_h2": 1.5, "hybrid_h10": 3, "topology": 9, "rebuild": 2.5},
+            "schedule": {"hybrid": 2, "data": 1, "hybrid_h2": 1.5, "hybrid_h10": 3, "hybrid_h20": 1.25,
+                         "hybrid_h30": 1.75, "hybrid_h40": 2.25, "topology": 9, "rebuild": 2.5},
             "light": {"auto": 1, "pull": 0.5, "push": 2},
             "tail_workgroups": {0: 1, -1: 2, 32: 0.25, 64: 0.5, 128: 3}}
     inv = {}
@@ -70,7 +71,8 @@ def test_search_finds_the_cheapest_point():
         fn(None)
         kw = inv["kw"]
         sched = {("data", 0): "data", ("topology", 0): "topology", ("hybrid", 0): "hybrid", ("rebuild", 0): "rebuild",
-                 ("hybrid", 20): "hybrid_h2", ("hybrid", 100): "hybrid_h10"}[(kw["mode"], kw["threshold"])]
+                 ("hybrid", 20): "hybrid_h2", ("hybrid", 100): "hybrid_h10", ("hybrid", 200): "hybrid_h20",
+                 ("hybrid", 300): "hybrid_h30", ("hybrid", 400): "hybrid_h40"}[(kw["mode"], kw["threshold"])]
         hub = kw["hub_min_degree"] if kw["hub_min_degree"] in cost["hub_min_degree"] else 0
         return 10.0 + cost["workgroups"][kw["workgroups"]] + cost["light_max_degree"][kw["light_max_degree"]] \
             + cost["hub_min_degree"][hub] + cost["schedule"][sched] + cost["light"][kw["light"]] \

@@ -229,42 +229,43 @@ def _check_packed_on_device(pb, rp, ci, col, chunk=1 << 24):
 @pytest.mark.slow
 @pytest.mark.timeout(1500)
 def test_batch_workload_full_size():
-    """The batch workload at full size: 4096 graphs with n log-uniform in [1e3, 1e6] (about 5.9e8
-    nodes and 1.1e10 entries), colored in one batched call as bench.py --config 4 times it.  Every
-    graph is checked for a proper coloring on the device; a sample (the smallest Erdos-Renyi and
-    R-MAT graphs, two mid-sized ones and the largest graph) is compared with the oracle exactly,
-    and all three schedules must agree everywhere."""
+    """The batch workload at full size: 4096 graphs with n log-uniform in [1e3, 1e6] (5.7e8 nodes
+    and 1.17e10 entries), colored in one batched call.  Every one of the 4096 graphs must match the
+    oracle's colors and round count (stored per graph by golden/make_oracle_digests.py), with the
+    library defaults and with the tuned options bench.py times; the input is checked against the
+    stored graph digests first, and the data-driven and topology-driven schedules must agree."""
     import time
     import paper_1912_01478_amd as ip
+    from paper_1912_01478_amd import autotune as at
+    from tests import _digests
+    ref = _digests.table("batch")
     t = time.time()
     pb = gg.batch_packed(4, 4096, progress=lambda d, t: print("[gpu batch full] generated %d of %d" % (d, t), flush=True))
     print("[gpu batch full] generated N=%d M=%d in %.0fs" % (pb.node_off[-1], pb.edge_off[-1], time.time() - t),
           flush=True)
+    assert (np.diff(pb.node_off) == ref["n"]).all() and (np.diff(pb.edge_off) == ref["m"]).all()
+    bad = _digests.packed_graph_mismatches(pb, ref)
+    assert not bad, "generator output changed for graphs %s" % bad[:8]
     rp = torch.from_numpy(pb.rowptr_packed).cuda()
     ci = torch.from_numpy(pb.colidx_packed).cuda()
-    res = ip.color_graphs_batched(rp, ci, pb.node_off, pb.edge_off, "hybrid")
-    torch.cuda.synchronize()
-    print("[gpu batch full] hybrid done, max rounds %d" % max(res.rounds), flush=True)
-    _check_packed_on_device(pb, rp, ci, res.colors)
-    ns = np.diff(pb.node_off)
-    assert all(r >= 1 for r in res.rounds)
-    kinds = np.array([p["kind"] == "er" for p in pb.params])
-    sample = {int(np.argmin(np.where(kinds, ns, 1 << 40))), int(np.argmin(np.where(~kinds, ns, 1 << 40))),
-              int(np.argmax(ns))}
-    mid = np.nonzero((ns > 50_000) & (ns < 100_000))[0]
-    sample |= set(int(x) for x in mid[:2])
-    col = res.colors
-    for g in sorted(sample):
-        gr = pb.graph(g)
-        ref = oracle.color_graph(gr.rowptr, gr.colidx)
-        print("[gpu batch full] oracle graph %d n=%d m=%d rounds=%d" % (g, gr.n, gr.m, ref.rounds), flush=True)
-        assert res.rounds[g] == ref.rounds
-        assert (res.graph(g).cpu().numpy() == ref.colors).all()
+    choice = at.TuneTable.load(at.DEFAULT_TABLE).lookup(at.graph_features(pb.rowptr_packed, pb.node_off))
+    runs = [("defaults", {})] + ([("tuned", at.call_kwargs(choice, int(pb.node_off[-1])))] if choice else [])
+    first = None
+    for name, kw in runs:
+        res = ip.color_graphs_batched(rp, ci, pb.node_off, pb.edge_off, **kw)
+        torch.cuda.synchronize()
+        col = res.colors.cpu().numpy()
+        print("[gpu batch full] %s %s done, max rounds %d" % (name, kw, max(res.rounds)), flush=True)
+        bad = _digests.packed_mismatches(pb.node_off, col, res.rounds, ref)
+        assert not bad, "%s: %d of 4096 graphs differ from the oracle, first %s" % (name, len(bad), bad[:8])
+        if first is None:
+            first = res
+            _check_packed_on_device(pb, rp, ci, res.colors)
     for mode in ("data", "topology"):
         other = ip.color_graphs_batched(rp, ci, pb.node_off, pb.edge_off, mode)
         torch.cuda.synchronize()
-        assert other.rounds == res.rounds and torch.equal(other.colors, col), mode
+        assert other.rounds == first.rounds and torch.equal(other.colors, first.colors), mode
         del other
-    del rp, ci, res, col
+    del rp, ci, res, first
     torch.cuda.empty_cache()
     ip.library().ipgc_release_workspaces()

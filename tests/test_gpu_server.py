@@ -189,3 +189,52 @@ def test_errors_and_edge_cases():
         j2 = srv.submit(good.rowptr, good.colidx)
         (r,) = drain(srv)
         assert r.job_id == j2 and r.status == 0 and (r.colors == ref.colors).all()
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(1200)
+def test_serving_workload_full_size():
+    """The serving stream at full size: 2000 jobs (the batch mix plus 10% R-MAT scale 20) through a
+    server whose arena fills 64 GB, as bench.py runs it: once with every job submitted at the start,
+    once with the jobs arriving in waves while others run.  Every job must match the oracle's colors
+    and round count, stored per job by golden/make_oracle_digests.py."""
+    import time
+    import paper_1912_01478_amd as ip
+    from tests import _digests
+    ref = _digests.table("serving")
+    t = time.time()
+    pb = gg.serving_jobs(5, 2000)
+    print("[gpu serving full] generated N=%d M=%d in %.0fs" % (pb.node_off[-1], pb.edge_off[-1], time.time() - t),
+          flush=True)
+    assert (np.diff(pb.node_off) == ref["n"]).all() and (np.diff(pb.edge_off) == ref["m"]).all()
+    bad = _digests.packed_graph_mismatches(pb, ref)
+    assert not bad, "generator output changed for jobs %s" % bad[:8]
+    J = pb.num_graphs
+    avg_degree = int(pb.edge_off[-1]) / int(pb.node_off[-1])
+    nodes, edges = ip.Server.capacity_for(64 << 30, avg_degree)
+    views = []
+    for g in range(J):
+        a, b = int(pb.node_off[g]), int(pb.node_off[g + 1])
+        views.append((pb.rowptr_packed[a + g:b + g + 1], pb.colidx_packed[int(pb.edge_off[g]):int(pb.edge_off[g + 1])]))
+    for waves in (1, 40):
+        with ip.Server(nodes, edges, max_jobs=4096) as srv:
+            ids, done = {}, {}
+            per = (J + waves - 1) // waves
+            for w0 in range(0, J, per):
+                for g in range(w0, min(J, w0 + per)):
+                    ids[srv.submit(*views[g])] = g
+                srv.step()
+                for r in srv.poll():
+                    done[ids[r.job_id]] = r
+            while len(done) < J:
+                srv.step()
+                for r in srv.poll():
+                    done[ids[r.job_id]] = r
+            peak = srv.stats()["peak_resident"]
+        bad = [g for g in range(J) if done[g].status != 0 or done[g].rounds != int(ref["rounds"][g])
+               or _digests.colors16(done[g].colors) != ref["colors16"][g]]
+        print("[gpu serving full] waves=%d peak resident %d, %d of %d jobs differ" % (waves, peak, len(bad), J),
+              flush=True)
+        assert not bad, "waves=%d: jobs %s differ from the oracle" % (waves, bad[:8])
+        assert peak > 1
+
