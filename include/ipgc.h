@@ -194,6 +194,34 @@ int ipgc_color_graph_ex(const int32_t *csr_rowptr, const int32_t *csr_colidx, in
                         ipgc_trace *trace);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * coloring as ipgc_color_graph_ex, with every piece of workspace carved from
+ * one static device array of IPGC_NOALLOC_SCRATCH_BYTES that the library's
+ * code object holds on each GPU it runs on (until the process ends).  The call
+ * makes no hipMalloc, hipFree, pinned-host or event allocation; the caller
+ * passes the CSR and out_colors as for ipgc_color_graph_ex.
+ *
+ * The workspace of a graph takes about 46 bytes per node, 5 bytes per CSR
+ * entry (9 with IPGC_VALIDATE_FULL) and 25 KiB per round workgroup (one per
+ * 4096 nodes, at most 256 on MI355X): 256 MiB hold, for example, every graph
+ * of up to 10^6 nodes and 32 * 10^6 entries.  A graph that does not fit
+ * returns IPGC_ETOOBIG before any device work.  options->profile must be NULL
+ * (IPGC_EINVAL): a profile needs events and a tick buffer.
+ *
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents (the call clears what must start at zero).  The library serializes
+ * its own calls per process and the call blocks until the result is complete,
+ * so calls from one process never overlap; work that another party enqueues
+ * into the same array would race.  Other arguments, errors and blocking are
+ * as for ipgc_color_graph_ex.
+ */
+#define IPGC_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int ipgc_color_graph_noalloc(const int32_t *csr_rowptr, const int32_t *csr_colidx, int64_t n, int64_t m, int mode,
+                             const ipgc_options *options, void *stream, int32_t *out_colors, int32_t *out_rounds,
+                             ipgc_trace *trace);
+
+/*
  * Color many graphs in one launch (the batched form of ipgc_color_graph).  The
  * graphs run together as one disjoint union; each one gets exactly the colors
  * and round count it gets alone.  One schedule decision is made per round for

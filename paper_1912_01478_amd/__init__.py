@@ -30,12 +30,16 @@ VALIDATE_NONE = 1
 VALIDATE_RANGES = 2
 VALIDATE_FULL = 3
 
+# Size of the static device array that ipgc_color_graph_noalloc carves its workspace from
+# (IPGC_NOALLOC_SCRATCH_BYTES in include/ipgc.h).
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
 OK, EINVAL, ETOOBIG, EBADCSR, ENOMEM, EHIP, ELIMIT, ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS = {0: "IPGC_OK", -1: "IPGC_EINVAL", -2: "IPGC_ETOOBIG", -3: "IPGC_EBADCSR", -4: "IPGC_ENOMEM",
           -5: "IPGC_EHIP", -6: "IPGC_ELIMIT", -7: "IPGC_ECANCELED"}
 
 # Every symbol the header declares; the tests check that the library exports all of them.
-EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_color_graphs_batched",
+EXPORTS = ("ipgc_color_graph", "ipgc_color_graph_ex", "ipgc_color_graph_noalloc", "ipgc_color_graphs_batched",
            "ipgc_last_error",
            "ipgc_kernel_name", "ipgc_unit_name", "ipgc_version", "ipgc_release_workspaces", "ipgc_server_create",
            "ipgc_server_submit", "ipgc_server_step", "ipgc_server_poll", "ipgc_server_stats_get",
@@ -128,6 +132,9 @@ def library() -> ctypes.CDLL:
         lib.ipgc_color_graph_ex.restype = i32
         lib.ipgc_color_graph_ex.argtypes = [vp, vp, i64, i64, i32, ctypes.POINTER(Options), vp, vp,
                                             ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Trace)]
+        lib.ipgc_color_graph_noalloc.restype = i32
+        lib.ipgc_color_graph_noalloc.argtypes = [vp, vp, i64, i64, i32, ctypes.POINTER(Options), vp, vp,
+                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(Trace)]
         lib.ipgc_color_graphs_batched.restype = i32
         lib.ipgc_color_graphs_batched.argtypes = [i64, vp, vp, vp, vp, i32, ctypes.POINTER(Options), vp, vp, vp,
                                                   ctypes.POINTER(Trace)]
@@ -365,6 +372,42 @@ def color_graph_raw(rowptr_ptr: int, colidx_ptr: int, n: int, m: int, mode: int,
                                     ctypes.c_void_p(out_ptr), ctypes.byref(rounds))
     _check(rc)
     return rounds.value
+
+
+def color_graph_noalloc(rowptr, colidx, mode="hybrid", *, out, stream=None, threshold: int = 0,
+                        light_max_degree: int = 0, hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT,
+                        stepped: bool = False, trace: bool = False, workgroups: int = 0, light: str = "auto",
+                        racy: bool = False, tail_workgroups: int = 0) -> Coloring:
+    """``color_graph`` through ``ipgc_color_graph_noalloc``: the library allocates no device memory
+    (its workspace is a static array of NOALLOC_SCRATCH_BYTES per GPU), so ``out`` (int32[n] on
+    the graph's device) must be given.  A graph whose workspace does not fit raises IPGC_ETOOBIG.
+    No profile; other arguments as for ``color_graph``."""
+    import torch
+
+    if rowptr.dtype != torch.int32 or colidx.dtype != torch.int32:
+        raise TypeError("rowptr and colidx must be int32")
+    if not (rowptr.is_cuda and colidx.is_cuda):
+        raise ValueError("rowptr and colidx must be device tensors")
+    if not (rowptr.is_contiguous() and colidx.is_contiguous()):
+        raise ValueError("rowptr and colidx must be contiguous (a copy would allocate)")
+    n = rowptr.numel() - 1
+    m = colidx.numel()
+    if n < 0:
+        raise ValueError("rowptr needs n+1 >= 1 entries")
+    if out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() or out.device != rowptr.device:
+        raise ValueError("out must be a contiguous int32 tensor of n entries on the graph's device")
+    call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, n, 0, 0, workgroups, light,
+                 racy, tail_workgroups)
+    rounds = ctypes.c_int32(-1)
+    if stream is None:
+        stream = torch.cuda.current_stream(rowptr.device)
+    with torch.cuda.device(rowptr.device):
+        rc = library().ipgc_color_graph_noalloc(
+            ctypes.c_void_p(rowptr.data_ptr()), ctypes.c_void_p(colidx.data_ptr() if m else 0), n, m,
+            _mode(mode), ctypes.byref(call.opts), ctypes.c_void_p(stream.cuda_stream),
+            ctypes.c_void_p(out.data_ptr() if n else 0), ctypes.byref(rounds), call.trace_ref())
+    _check(rc)
+    return call.finish(Coloring(out, rounds.value))
 
 
 def pack_graphs(graphs):

@@ -621,6 +621,85 @@ int batch_impl(int64_t graphs, const int64_t *node_off, const int64_t *edge_off,
     return IPGC_OK;
 }
 
+// ------------------------------------------------------------ static scratch (no allocation)
+//
+// ipgc_color_graph_noalloc carves its workspace out of one file-scope device
+// array instead of allocating it.  In host code `scratch` is only the host-side
+// stand-in of the array: its device address on each GPU comes from
+// hipGetSymbolAddress, once per device, and only that address reaches kernels.
+
+constexpr size_t kStaticScratchBytes = IPGC_NOALLOC_SCRATCH_BYTES;
+constexpr int kStaticMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+void *g_scratch_ptr[kStaticMaxDevices];          // device address of `scratch` per device (null: not yet looked up)
+Workspace g_static_ws[kStaticMaxDevices];        // the carved workspace per device (borrowed buffers only)
+
+// The device address of this device's copy of `scratch` (caller holds g_mutex, dev is current).
+int static_scratch(int dev, unsigned char **out) {
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(IPGC_EHIP, "hipGetSymbolAddress returned no address for the static scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_ptr[dev]);
+    return IPGC_OK;
+}
+
+int color_noalloc_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t m, int mode,
+                       const ipgc_options *opt, hipStream_t s, int32_t *out_colors, int32_t *out_rounds,
+                       ipgc_trace *trace) {
+    if (!out_rounds) return fail(IPGC_EINVAL, "out_rounds is NULL");
+    *out_rounds = -1;
+    if (n < 0 || m < 0) return fail(IPGC_EINVAL, "negative size (n=%lld, m=%lld)", (long long)n, (long long)m);
+    if (n >= INT32_MAX || m >= INT32_MAX)
+        return fail(IPGC_ETOOBIG, "n=%lld or m=%lld exceeds the int32 CSR", (long long)n, (long long)m);
+    Params P;
+    TRY(parse_options(opt, mode, &P));
+    // a profile records HIP events and a device tick buffer, which would have to be created
+    if (P.prof) return fail(IPGC_EINVAL, "ipgc_color_graph_noalloc takes no profile (it would need allocations)");
+    if (trace) trace->recorded = 0;
+    if (n == 0) {
+        *out_rounds = 0;
+        g_err[0] = 0;
+        return IPGC_OK;
+    }
+    if (!rowptr || !out_colors || (m > 0 && !colidx)) return fail(IPGC_EINVAL, "null device pointer");
+
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kStaticMaxDevices) return fail(IPGC_EINVAL, "device %d past the static scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_mutex);
+    unsigned char *base = nullptr;
+    TRY(static_scratch(dev, &base));
+    Workspace &ws = g_static_ws[dev];
+    int grid = 1, coop = 0;
+    TRY(round_grid(ws, dev, P, n, &grid, &coop));
+    int64_t span = 0;
+    int prep_grid = 0;
+    prep_layout(n, &span, &prep_grid);
+    size_t used = 0;
+    TRY(ws.carve(base, kStaticScratchBytes, n, m, grid, prep_grid, P.hub_min, P.full, &used));
+
+    int32_t ends[2];
+    HIP_TRY(hipMemcpyAsync(&ends[0], rowptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&ends[1], rowptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (ends[0] != 0 || ends[1] != m)
+        return fail(IPGC_EBADCSR, "rowptr[0]=%d rowptr[n]=%d, expected 0 and m=%lld", ends[0], ends[1], (long long)m);
+
+    DevT<int32_t> d{};
+    d.rowptr = rowptr;
+    d.colidx = colidx;
+    d.c = out_colors;
+    TRY(clear(ws.ct, sizeof(Counters), s));  // the array keeps the previous call's contents
+    TRY(run(ws, dev, s, P, d, n, m, grid, coop, out_rounds, trace));
+    g_err[0] = 0;
+    return IPGC_OK;
+}
+
 }  // namespace
 }  // namespace ipgc
 
@@ -644,6 +723,13 @@ int ipgc_color_graphs_batched(int64_t num_graphs, const int64_t *node_off, const
                               int32_t *out_rounds, ipgc_trace *trace) {
     IPGC_GUARD(ipgc::batch_impl(num_graphs, node_off, edge_off, rowptr_packed, colidx_packed, mode, options,
                                 (hipStream_t)stream, out_colors_packed, out_rounds, trace));
+}
+
+int ipgc_color_graph_noalloc(const int32_t *csr_rowptr, const int32_t *csr_colidx, int64_t n, int64_t m, int mode,
+                             const ipgc_options *options, void *stream, int32_t *out_colors, int32_t *out_rounds,
+                             ipgc_trace *trace) {
+    IPGC_GUARD(ipgc::color_noalloc_impl(csr_rowptr, csr_colidx, n, m, mode, options, (hipStream_t)stream, out_colors,
+                                        out_rounds, trace));
 }
 
 const char *ipgc_last_error(void) { return ipgc::g_err; }

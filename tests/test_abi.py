@@ -124,3 +124,11 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(pkg, "_lib", None)
     with pytest.raises(ImportError):
         pkg.library()
+
+
+def test_noalloc_scratch_size_matches_binding():
+    import paper_1912_01478_amd as pkg
+    text = open(HEADER).read()
+    m = re.search(r"#define\s+IPGC_NOALLOC_SCRATCH_BYTES\s+\((\d+)ull\s*<<\s*(\d+)\)", text)
+    assert m, "IPGC_NOALLOC_SCRATCH_BYTES not found"
+    assert int(m.group(1)) << int(m.group(2)) == pkg.NOALLOC_SCRATCH_BYTES
