@@ -443,7 +443,8 @@ def run_workload(args, torch, pkg, w, steps, warmup, cpu):
 
     # per-kernel profile, trace and round-step timeline of one more (untimed) call
     single = isinstance(w, SingleGraph)
-    prof = w.call(trace=True, profile_mask=0xFFFF, timeline=(3 * rounds + 4) if single else 0, **kw)
+    tl = {"timeline": 3 * rounds + 4} if single else {}  # the batched call has no timeline
+    prof = w.call(trace=True, profile_mask=0xFFFF, **tl, **kw)
     if single and parity is not None:
         parity = w.parity(prof)  # the traced call: also the per-round worklist sizes
     units = prof.profile["units"]

@@ -90,7 +90,7 @@ const char *const kUnitNames[kNumUnits] = {"assign_nodes",   "pull_entries", "ma
                                            "conflict_entries", "list_writes", "push_entries", "commits"};
 
 struct Workspace {
-    DBuf<int32_t> static_list, seg_list0, seg_list1, seg_cnt, block_cnt, trace, lstart, llen, lower;
+    DBuf<int32_t> static_list, seg_list0, seg_list1, seg_cnt, block_cnt, hub_pre, hub_cnt, trace, lstart, llen, lower;
     DBuf<HubRec> hub_won;
     DBuf<int64_t> seg_deg, block_deg, units, trace_deg;
     DBuf<int8_t> cls;
@@ -124,7 +124,11 @@ struct Workspace {
         TRY(f(seg_cnt, 2 * kNumClasses * (int64_t)kMaxRoundBlocks));
         TRY(f(seg_deg, 2 * kNumClasses * (int64_t)kMaxRoundBlocks));
         TRY(f(hub_won, std::min<int64_t>(n, m / ((int64_t)hub_min + 1) + 1)));
-        TRY(f(block_cnt, (int64_t)kNumClasses * prep_grid));
+        TRY(f(block_cnt, (int64_t)(kNumClasses + 1) * prep_grid));
+        // class-M nodes (degree above hub_min) + the total; two counts per row chunk of them
+        const int64_t hubs = std::min<int64_t>(n, m / ((int64_t)hub_min + 1));
+        TRY(f(hub_pre, hubs + 1));
+        TRY(f(hub_cnt, 2 * (hubs + m / kRingChunk + 1)));
         TRY(f(block_deg, (int64_t)kNumClasses * prep_grid));
         TRY(f(units, (int64_t)kNumUnits * kMaxRoundBlocks));
         TRY(f(trace, n));
@@ -174,6 +178,7 @@ struct Workspace {
 
     void release() {
         static_list.release(); seg_list0.release(); seg_list1.release(); seg_cnt.release(); hub_won.release();
+        hub_pre.release(); hub_cnt.release();
         block_cnt.release(); trace.release(); lstart.release(); llen.release(); lower.release();
         seg_deg.release(); block_deg.release(); units.release(); trace_deg.release(); cls.release();
         F.release(); mask.release(); pend.release(); ticks.release(); bar.release(); growptr.release(); node_off.release(); edge_off.release();
@@ -389,6 +394,8 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
     d.seg_deg[1] = ws.seg_deg.p + kNumClasses * kMaxRoundBlocks;
     d.hub_won = ws.hub_won.p;
     d.block_cnt = ws.block_cnt.p;
+    d.hub_pre = ws.hub_pre.p;
+    d.hub_cnt = ws.hub_cnt.p;
     d.block_deg = ws.block_deg.p;
     d.units = ws.units.p;
     d.ct = ws.ct;
@@ -434,13 +441,20 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
     d.discard = P.mode == IPGC_MODE_REBUILD ? 1 : 0;
     if (P.check_ids && n_light > 0) {
         TRY(pf.begin(kKindCheck));
-        k_check_light<<<(int)std::min<int64_t>(8192, (n_light + kPrepBlock - 1) / kPrepBlock), kPrepBlock, 0, s>>>(d);
+        k_check_light<<<(int)((n_light + kPrepBlock - 1) / kPrepBlock), kPrepBlock, 0, s>>>(d);  // a node per thread
         TRY(pf.end(kKindCheck));
         HIP_TRY(hipGetLastError());
     }
     if (n_wide > 0) {  // also checks the ids of the wide rows
+        const int64_t n_w = ws.host_ct->class_n[kW], n_hub = ws.host_ct->class_n[kM];
+        const int64_t hub_chunks = ws.host_ct->hub_chunks;
         TRY(pf.begin(kKindPrep));
-        k_prep_wide<<<(int)std::min<int64_t>(8192, (n_wide + 3) / 4), kPrepBlock, 0, s>>>(d);
+        if (n_w > 0) k_prep_wide<<<(int)std::min<int64_t>(8192, (n_w + 3) / 4), kPrepBlock, 0, s>>>(d);
+        if (n_hub > 0) {
+            const int blocks = (int)std::min<int64_t>(8192, (hub_chunks + 3) / 4);
+            k_prep_hubs<false><<<blocks, kPrepBlock, 0, s>>>(d);
+            k_prep_hubs<true><<<blocks, kPrepBlock, 0, s>>>(d);
+        }
         TRY(pf.end(kKindPrep));
         HIP_TRY(hipGetLastError());
     }
@@ -485,6 +499,7 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
                         "launch ran (%d workgroups)", P.barrier_ms, grid);
         return fail(IPGC_ELIMIT, "rounds did not finish");
     }
+    if (ws.host_ct->seg_overflow) return fail(IPGC_EHIP, "internal error: a worklist segment overflowed");
     const int32_t rounds = ws.host_ct->rounds;
     if (trace) {
         const int64_t k = std::min<int64_t>(trace->capacity, rounds);

@@ -79,6 +79,7 @@ constexpr int kLightMaxLimit = 32;       // thread-per-node pull uses a 64-bit m
 constexpr int kMaxXcc = 16;
 constexpr int kWideScanMax = 65536;      // rounds with at most this many active nodes scan rings 4 chunks a pass
 constexpr int kMaskColors = 64;          // colors 1..64 of committed neighbours are bits of a word per node
+constexpr int kRingChunk = 2048;         // row entries of a class-M node whose ring part one wavefront builds
 
 enum { kL = 0, kW = 1, kM = 2, kNumClasses = 3 };
 
@@ -136,6 +137,8 @@ struct Counters {
     int32_t hub_winners;              // hubs committed in the current round
     int32_t prev_discarded;           // the last round kept no worklist (discard mode, stepped launches)
     int32_t bad_full;                 // IPGC_VALIDATE_FULL: bit 0 self-loop, bit 1 duplicate, bit 2 no reverse entry
+    int32_t seg_overflow;             // a workgroup had more losers than its out segment holds (never expected)
+    int32_t hub_chunks;               // row chunks of kRingChunk entries over all class-M nodes
 };
 
 // A committed hub waiting for the push step.
@@ -151,6 +154,7 @@ struct HubRec {
 // the kernels see as one graph (the disjoint union) with global node ids.
 template <typename Off>
 struct DevT {
+    using OffT = Off;
     const Off *rowptr;       // row starts, n + 1 entries (a batch: union row starts)
     const int32_t *colidx;   // column indices (a batch: ids local to each graph)
     const int32_t *gbase;    // a batch: first global id of each node's graph (null for one graph)
@@ -173,7 +177,10 @@ struct DevT {
     int32_t *seg_cnt[2];     // [kNumClasses][grid] entries per segment
     int64_t *seg_deg[2];     // [kNumClasses][grid] degree sum per segment
     HubRec *hub_won;         // hubs committed in the current round
-    int32_t *block_cnt;      // [kNumClasses][prep grid] class counts per preparation workgroup
+    int32_t *block_cnt;      // [kNumClasses + 1][prep grid] class counts (then class-M row chunks) per
+                             // preparation workgroup
+    int32_t *hub_pre;        // class-M nodes in static-list order: first row chunk of each (+ the total)
+    int32_t *hub_cnt;        // per row chunk of a class-M node: its smaller neighbours of class L, of class W/M
     int64_t *block_deg;      // [kNumClasses][prep grid]
     int64_t *units;          // [kNumUnits][grid] work counters per round workgroup
     Counters *ct;
@@ -272,7 +279,7 @@ struct GridBarrier {
     // One-time setup: count the workgroups of every XCD (flat barrier with a
     // per-workgroup release and acquire; used once per launch).  False if the
     // wait gave up: the caller leaves the kernel.
-    __device__ bool setup(Barrier *bar, uint64_t lim) {
+    __device__ __forceinline__ bool setup(Barrier *bar, uint64_t lim) {
         __shared__ int s_ok;
         b = bar;
         limit = lim;
@@ -304,7 +311,7 @@ struct GridBarrier {
 
     // From now on only workgroups 0 .. g-1 take part (every one of them calls
     // this at the same point, between two barriers; the others have left).
-    __device__ void shrink(int g) {
+    __device__ __forceinline__ void shrink(int g) {
         __shared__ unsigned s_x[kMaxXcc];
         if (threadIdx.x < kMaxXcc) s_x[threadIdx.x] = 0;
         __syncthreads();
@@ -319,7 +326,7 @@ struct GridBarrier {
     // False if the wait gave up (the caller leaves the kernel).  A leader that
     // gives up does not release its XCD, so no workgroup goes on past a barrier
     // that not every workgroup reached.
-    __device__ bool sync() {
+    __device__ __forceinline__ bool sync() {
         __shared__ int s_ok;
         __builtin_amdgcn_s_waitcnt(0);  // this thread's stores have reached the XCD's L2
         __syncthreads();
@@ -463,6 +470,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_init(D d, int8_t *cls, int32_t s
     const int64_t lo = (int64_t)blockIdx.x * span, hi = std::min<int64_t>(lo + span, d.n);
     int cnt[kNumClasses] = {0, 0, 0};
     int64_t deg[kNumClasses] = {0, 0, 0};
+    int chunks = 0;  // row chunks of class-M nodes (their rings are built a chunk per wavefront)
     int bad = 0;
     for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
         // Round 1 assigns color 1 to every node (no neighbour is committed yet), so the state
@@ -478,14 +486,13 @@ __global__ __launch_bounds__(kPrepBlock) void k_init(D d, int8_t *cls, int32_t s
         d.pend[v] = k != kL ? 0u : dv >= 32 ? ~0u : (1u << dv) - 1u;
         cnt[k] += 1;
         deg[k] += dv;
+        if (k == kM) chunks += (int)((dv + kRingChunk - 1) / kRingChunk);
     }
     if (__ballot(bad) && lane_id() == 0) d.ct->bad_rows = 1;
-    __shared__ int s_cnt[kNumClasses];
+    __shared__ int s_cnt[kNumClasses + 1];
     __shared__ unsigned long long s_deg[kNumClasses];
-    if (threadIdx.x < kNumClasses) {
-        s_cnt[threadIdx.x] = 0;
-        s_deg[threadIdx.x] = 0;
-    }
+    if (threadIdx.x <= kNumClasses) s_cnt[threadIdx.x] = 0;
+    if (threadIdx.x < kNumClasses) s_deg[threadIdx.x] = 0;
     __syncthreads();
     for (int k = 0; k < kNumClasses; ++k) {
         const int64_t ds = wave_sum(deg[k]);
@@ -495,40 +502,56 @@ __global__ __launch_bounds__(kPrepBlock) void k_init(D d, int8_t *cls, int32_t s
             atomicAdd(&s_deg[k], (unsigned long long)ds);
         }
     }
+    const int64_t hs = wave_sum(chunks);
+    if (lane_id() == 0 && hs) atomicAdd(&s_cnt[kNumClasses], (int)hs);
     __syncthreads();
-    if (threadIdx.x < kNumClasses) {
-        d.block_cnt[threadIdx.x * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
-        d.block_deg[threadIdx.x * gridDim.x + blockIdx.x] = (int64_t)s_deg[threadIdx.x];
-    }
+    if (threadIdx.x <= kNumClasses) d.block_cnt[threadIdx.x * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
+    if (threadIdx.x < kNumClasses) d.block_deg[threadIdx.x * gridDim.x + blockIdx.x] = (int64_t)s_deg[threadIdx.x];
 }
 
 // Prefix of the per-workgroup class counts (one workgroup): static-list
-// offsets per preparation workgroup, class sizes and regions, segment sizes.
+// offsets per preparation workgroup, class sizes and regions, segment sizes,
+// and the offsets of each workgroup's first class-M row chunk.  Thread t sums
+// the counts of workgroups [t*per, (t+1)*per) (independent loads), one
+// workgroup scan combines the sums, and thread t writes its range's offsets.
 template <class D>
 __global__ __launch_bounds__(1024) void k_offsets(D d, int32_t prep_grid) {
+    const int32_t per = (prep_grid + (int32_t)blockDim.x - 1) / (int32_t)blockDim.x;
+    const int32_t b0 = min<int32_t>(prep_grid, (int32_t)threadIdx.x * per), b1 = min<int32_t>(prep_grid, b0 + per);
+    __shared__ unsigned long long s_d;
     int32_t base = 0;
-    for (int k = 0; k < kNumClasses; ++k) {
-        int64_t dsum = 0;
-        for (int32_t b0 = 0; b0 < prep_grid; b0 += blockDim.x) {
-            const int32_t b = b0 + threadIdx.x;
-            const int x = b < prep_grid ? d.block_cnt[k * prep_grid + b] : 0;
-            int tot;
-            const int ex = block_scan(x, &tot);
-            if (b < prep_grid) d.block_cnt[k * prep_grid + b] = base + ex;
-            base += tot;
-            const int64_t ds = b < prep_grid ? d.block_deg[k * prep_grid + b] : 0;
-            dsum += wave_sum(ds);  // lane 0 of each wave holds its part
+    for (int k = 0; k <= kNumClasses; ++k) {  // the classes, then the class-M row chunks
+        int32_t *row = d.block_cnt + (int64_t)k * prep_grid;
+        int32_t sum = 0;
+        int64_t ds = 0;
+        for (int32_t b = b0; b < b1; ++b) {
+            sum += row[b];
+            if (k < kNumClasses) ds += d.block_deg[(int64_t)k * prep_grid + b];
         }
-        __shared__ unsigned long long s_d;
+        int tot;
+        const int ex = block_scan(sum, &tot);
+        int32_t acc = (k < kNumClasses ? base : 0) + ex;
+        for (int32_t b = b0; b < b1; ++b) {
+            const int32_t x = row[b];
+            row[b] = acc;
+            acc += x;
+        }
+        if (k == kNumClasses) {
+            if (threadIdx.x == 0) d.ct->hub_chunks = tot;
+            break;
+        }
+        base += tot;
         if (threadIdx.x == 0) s_d = 0;
         __syncthreads();
-        if (lane_id() == 0) atomicAdd(&s_d, (unsigned long long)dsum);
+        const int64_t wsum = wave_sum(ds);
+        if (lane_id() == 0 && wsum) atomicAdd(&s_d, (unsigned long long)wsum);
         __syncthreads();
         if (threadIdx.x == 0) d.ct->class_deg[k] = (int64_t)s_d;
         __syncthreads();
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        // block_cnt now holds exclusive offsets; class boundaries from the last workgroup's offsets
+        // block_cnt now holds exclusive offsets; class boundaries from workgroup 0's offsets
         int32_t off[kNumClasses + 1];
         off[0] = 0;
         for (int k = 1; k < kNumClasses; ++k) off[k] = d.block_cnt[k * prep_grid];
@@ -540,19 +563,25 @@ __global__ __launch_bounds__(1024) void k_offsets(D d, int32_t prep_grid) {
             const int32_t cap = (d.ct->class_n[k] + d.grid - 1) / d.grid + kRoundBlock;
             d.ct->seg_cap[k] = cap;
             d.ct->seg_off[k] = so;
-            so += cap * d.grid;
+            so += (int64_t)cap * d.grid;
         }
         d.ct->static_off[kNumClasses] = d.n;
         d.ct->seg_off[kNumClasses] = so;
+        if (d.hub_pre) d.hub_pre[d.ct->class_n[kM]] = d.ct->hub_chunks;
     }
 }
 
 // The static list: every node grouped by class, ascending id within a class.
+// For class-M nodes also the first of their row chunks (hub_pre, in the same
+// order), for k_prep_hubs.
 template <class D>
 __global__ __launch_bounds__(kPrepBlock) void k_fill_static(D d, int32_t span) {
     const int64_t lo = (int64_t)blockIdx.x * span, hi = std::min<int64_t>(lo + span, d.n);
     int32_t base[kNumClasses];
     for (int k = 0; k < kNumClasses; ++k) base[k] = d.block_cnt[k * gridDim.x + blockIdx.x];
+    int32_t cbase = d.block_cnt[kNumClasses * gridDim.x + blockIdx.x];  // this workgroup's first chunk
+    const int32_t m0 = d.ct->static_off[kM];
+    const bool hubs = d.hub_pre && d.ct->class_n[kM] > 0;
     for (int64_t v0 = lo; v0 < hi; v0 += blockDim.x) {
         const int64_t v = v0 + threadIdx.x;
         const int k = v < hi ? d.cls[v] : -1;
@@ -560,6 +589,14 @@ __global__ __launch_bounds__(kPrepBlock) void k_fill_static(D d, int32_t span) {
             int tot;
             const int ex = block_scan(k == q, &tot);
             if (k == q) d.static_list[base[q] + ex] = (int32_t)v;
+            if (q == kM && hubs) {
+                int ch = 0;
+                if (k == kM) ch = (int)((d.rowptr[v + 1] - d.rowptr[v] + kRingChunk - 1) / kRingChunk);
+                int ctot;
+                const int cex = block_scan(ch, &ctot);
+                if (k == kM) d.hub_pre[base[kM] - m0 + ex] = cbase + cex;
+                cbase += ctot;
+            }
             base[q] += tot;
         }
     }
@@ -639,12 +676,13 @@ __device__ void ring_build_wave(const D &d, int32_t v, int64_t lo, int64_t hi, i
     }
 }
 
-// Rings of every W/M node (a wavefront each), with the checks of their rows.
+// Rings of the class-W nodes (a wavefront each; with hub_pre unset, of the
+// class-M nodes too), with the checks of their rows.
 template <class D>
 __global__ __launch_bounds__(kPrepBlock) void k_prep_wide(D d) {
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
-    const int32_t nWide = d.ct->class_n[kW] + d.ct->class_n[kM];
+    const int32_t nWide = d.ct->class_n[kW] + (d.hub_pre ? 0 : d.ct->class_n[kM]);
     const int32_t *listWide = d.static_list + d.ct->static_off[kW];
     int bad = 0, unsorted = 0;
     for (int64_t i = gw; i < nWide; i += nw) {
@@ -653,6 +691,110 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep_wide(D d) {
     }
     if (__ballot(bad) && lane_id() == 0) d.ct->bad_ids = 1;
     if (__ballot(unsorted) && lane_id() == 0) d.ct->unsorted = 1;
+}
+
+// Part of class-M node v's ring from row entries [k0, k1) of its row [b, e),
+// by one wavefront.  Counting pass (WRITE false): the chunk's smaller
+// neighbours of class L (*nl) and of class W/M (*nh), with the checks of its
+// entries.  Writing pass: the same neighbours, in row order, at ring positions
+// posL.. (class L, from position 0 of the node's region upward) and posH..
+// (class W/M, in [d - NH, d) for NH of them over the whole row), so the ring is
+// laid out exactly as ring_build_wave lays it out.
+template <bool WRITE, class D>
+__device__ void ring_build_chunk(const D &d, int32_t v, int64_t b, int64_t e, int64_t k0, int64_t k1, int64_t lo,
+                                 int64_t hi, int32_t posL, int32_t posH, int &bad, int &unsorted, int32_t *nl_out,
+                                 int32_t *nh_out) {
+    const int lane = lane_id();
+    int32_t nl = 0, nh = 0;
+    for (int64_t p = k0; p < k1; p += kWave) {
+        const int64_t k = p + lane;
+        int q = -1;
+        int32_t u = -1;
+        if (k < k1) {
+            const int64_t ug = (int64_t)d.colidx[k] + lo;
+            const bool ok = ug >= lo && ug < hi;
+            if (!WRITE) {
+                bad |= !ok;
+                if (k + 1 < e) unsorted |= ((int64_t)d.colidx[k + 1] + lo <= ug);
+            }
+            u = (int32_t)ug;
+            if (ok && u < v) q = d.cls[u] == kL ? 0 : 1;
+        }
+        const uint64_t m0 = __ballot(q == 0), m1 = __ballot(q == 1);
+        if (WRITE) {
+            if (q == 0) d.lower[b + posL + nl + __popcll(m0 & lanes_below())] = u;
+            if (q == 1) d.lower[b + posH + nh + __popcll(m1 & lanes_below())] = u;
+        }
+        nl += __popcll(m0);
+        nh += __popcll(m1);
+    }
+    *nl_out = nl;
+    *nh_out = nh;
+}
+
+// Rings of the class-M nodes: their rows are cut into chunks of kRingChunk
+// entries (hub_pre: first chunk of each node, in static-list order), and
+// wavefront w of the grid takes chunks w, w + waves, ...; a node of degree 10^5
+// costs about as much as fifty of degree 2048 instead of one wavefront walking
+// its whole row.  Two launches: WRITE false counts each chunk's parts into
+// hub_cnt and checks the entries; WRITE true places them from the prefix of
+// the node's chunk counts and sets the ring's start and length.
+template <bool WRITE, class D>
+__global__ __launch_bounds__(kPrepBlock) void k_prep_hubs(D d) {
+    const int lane = lane_id();
+    const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int32_t nM = d.ct->class_n[kM];
+    const int32_t *listM = d.static_list + d.ct->static_off[kM];
+    const int32_t total = d.hub_pre[nM];
+    int bad = 0, unsorted = 0;
+    for (int64_t g = gw; g < total; g += nw) {
+        // the node h with hub_pre[h] <= g < hub_pre[h + 1], by a 64-way search (every node has a chunk)
+        int64_t lo = 0, hi = nM;
+        while (hi - lo > 1) {
+            const int64_t step = (hi - lo + kWave - 1) / kWave;
+            const int64_t idx = lo + lane * step;
+            const uint64_t le = __ballot(idx < hi && d.hub_pre[idx] <= g);
+            lo += (int64_t)(63 - __clzll((unsigned long long)le)) * step;
+            hi = min(hi, lo + step);
+        }
+        const int32_t v = listM[lo];
+        const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
+        const int32_t c0 = d.hub_pre[lo], c1 = d.hub_pre[lo + 1];
+        const int64_t k0 = b + (g - c0) * (int64_t)kRingChunk, k1 = min<int64_t>(k0 + kRingChunk, e);
+        int32_t nl, nh;
+        if (!WRITE) {
+            ring_build_chunk<false>(d, v, b, e, k0, k1, d.base(v), d.id_end(v), 0, 0, bad, unsorted, &nl, &nh);
+            if (lane == 0) {
+                d.hub_cnt[2 * g] = nl;
+                d.hub_cnt[2 * g + 1] = nh;
+            }
+        } else {
+            int64_t bl = 0, bh = 0, tl = 0, th = 0;  // this node's chunks before g, and all of them
+            for (int64_t c = c0 + lane; c < c1; c += kWave) {
+                const int32_t x = d.hub_cnt[2 * c], y = d.hub_cnt[2 * c + 1];
+                bl += c < g ? x : 0;
+                bh += c < g ? y : 0;
+                tl += x;
+                th += y;
+            }
+            bl = wave_sum(bl);
+            bh = wave_sum(bh);
+            tl = wave_sum(tl);
+            th = wave_sum(th);
+            const int32_t cap = (int32_t)(e - b);
+            ring_build_chunk<true>(d, v, b, e, k0, k1, d.base(v), d.id_end(v), (int32_t)bl,
+                                   (int32_t)(cap - th + bh), bad, unsorted, &nl, &nh);
+            if (g == c0 && lane == 0) {
+                d.lstart[v] = th > 0 ? (int32_t)(cap - th) : 0;
+                d.llen[v] = (int32_t)(tl + th);
+            }
+        }
+    }
+    if (!WRITE) {
+        if (__ballot(bad) && lane == 0) d.ct->bad_ids = 1;
+        if (__ballot(unsorted) && lane == 0) d.ct->unsorted = 1;
+    }
 }
 
 // ============================================================== full validation
@@ -801,16 +943,36 @@ struct ClassView {
     int32_t cap;          // segmented: entries per segment
     int32_t total;
 
-    __device__ __forceinline__ int32_t at(int32_t i) const {
-        if (!pre) return base[i];
-        // the segment s with pre[s] <= i < pre[s+1]
-        int lo = 0, hi = gridDim.x;
+    // the segment s in [lo, hi) with pre[s] <= i < pre[s + 1] (pre[lo] <= i is assumed)
+    __device__ __forceinline__ int seg_of(int32_t i, int lo, int hi) const {
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (pre[mid] <= i) lo = mid;
             else hi = mid;
         }
-        return base[(int64_t)lo * cap + (i - pre[lo])];
+        return lo;
+    }
+
+    // item i, found among segments [lo, hi) (see range)
+    __device__ __forceinline__ int32_t at_in(int32_t i, int lo, int hi) const {
+        if (!pre) return base[i];
+        const int s = seg_of(i, lo, hi);
+        return base[(int64_t)s * cap + (i - pre[s])];
+    }
+
+    __device__ __forceinline__ int32_t at(int32_t i) const { return at_in(i, 0, gridDim.x); }
+
+    // Segments [*lo, *hi) holding items a..b (a <= b < total; the same for every lane of a
+    // wavefront), so that each lane's search for an item in between covers only those: in large
+    // rounds a wavefront's items lie in one or two segments.
+    __device__ __forceinline__ void range(int32_t a, int32_t b, int *lo, int *hi) const {
+        if (!pre) {
+            *lo = 0;
+            *hi = 1;
+            return;
+        }
+        *lo = seg_of(a, 0, gridDim.x);
+        *hi = seg_of(b, *lo, gridDim.x) + 1;
     }
 };
 
@@ -826,7 +988,7 @@ struct RoundIn {
 // Segments past the first `writers` (workgroups that had left the round loop
 // when the list was written) count as empty.
 template <class D>
-__device__ void load_segments(const D &d, int src, int32_t (*pre)[kMaxRoundBlocks + 1], int writers) {
+__device__ __forceinline__ void load_segments(const D &d, int src, int32_t (*pre)[kMaxRoundBlocks + 1], int writers) {
     static_assert(kNumClasses == 3, "one fused scan covers the three classes");
     const int nb = gridDim.x;
     int x[kNumClasses], ex[kNumClasses], tot[kNumClasses];
@@ -840,7 +1002,7 @@ __device__ void load_segments(const D &d, int src, int32_t (*pre)[kMaxRoundBlock
 }
 
 template <class D>
-__device__ RoundIn round_view(const D &d, int r, int32_t (*pre)[kMaxRoundBlocks + 1]) {
+__device__ __forceinline__ RoundIn round_view(const D &d, int r, int32_t (*pre)[kMaxRoundBlocks + 1]) {
     RoundIn in;
     int32_t tot[kNumClasses];
     if (r == 1) {
@@ -880,13 +1042,13 @@ __device__ __forceinline__ unsigned long long *unit_totals() {
 // d.units[i][block] at the end of the kernel.
 struct Units {
     uint32_t u[kNumUnits];
-    __device__ Units() {
+    __device__ __forceinline__ Units() {
         for (int i = 0; i < kNumUnits; ++i) u[i] = 0;
         if (threadIdx.x < kNumUnits) unit_totals()[threadIdx.x] = 0;
         __syncthreads();
     }
     // every thread of the workgroup calls this at the same point
-    __device__ void fold() {
+    __device__ __forceinline__ void fold() {
         unsigned long long *tot = unit_totals();
         for (int i = 0; i < kNumUnits; ++i) {
             const int64_t s = wave_sum((int64_t)u[i]);
@@ -895,7 +1057,7 @@ struct Units {
         }
     }
     template <class D>
-    __device__ void flush(const D &d) {
+    __device__ __forceinline__ void flush(const D &d) {
         fold();
         __syncthreads();
         if (threadIdx.x < kNumUnits) d.units[threadIdx.x * gridDim.x + blockIdx.x] += (int64_t)unit_totals()[threadIdx.x];
@@ -943,40 +1105,306 @@ __device__ __forceinline__ void map_assign_wave(const D &d, int32_t v, Units &un
     }
 }
 
+// Class L nodes (degree <= light_max <= 32) run a lane each, kLightK of them in flight per lane:
+// each step of the per-node chain (worklist entry, state and row bounds, row entries, neighbour
+// states) is issued for all of a lane's nodes before any result is used, so one lane keeps up to
+// kLightK * kLightC loads outstanding where a node alone has a chain of dependent ones.  A
+// wavefront takes items b0 + j * 64 + lane (j < kLightK) of a block of 64 * kLightK consecutive
+// items, so every load of a step is coalesced across the wavefront when the items are.
+constexpr int kLightK = 2;  // nodes per lane
+constexpr int kLightC = 4;  // row entries per node per pass
+
+// Tentative colors of the class-L items (Section II-C, first fit): the first zero bit of the
+// node's color mask (push modes: committed neighbours set bit t - 1; d <= 32 neighbours leave a
+// zero among the first 33 bits), or of a mask of the committed colors read from the
+// neighbours' states (pull modes).  TOPO: a sweep over the static list, committed nodes skipped.
+template <bool TOPO, class D>
+__device__ __forceinline__ void light_assign(const D &d, const ClassView &cv, Units &un, int G) {
+    using Off = typename D::OffT;
+    constexpr int K = kLightK, C = kLightC;
+    const int lane = lane_id();
+    // blocks of 64 * K items go round the workgroups (block i to workgroup i mod G), so no
+    // workgroup takes more than total / G + 64 * K * (1 + 1/G) items: its out segments hold them
+    const int64_t gw = (int64_t)(threadIdx.x / kWave) * G + blockIdx.x;
+    const int64_t nw = (int64_t)G * (blockDim.x / kWave);
+    const int32_t total = cv.total;
+    for (int64_t b0 = gw * (kWave * K); b0 < total; b0 += nw * (kWave * K)) {
+        int slo, shi;
+        cv.range((int32_t)b0, (int32_t)min<int64_t>(b0 + kWave * K, total) - 1, &slo, &shi);
+        int32_t v[K];
+        uint32_t act = 0;  // bit j: item j of this lane is an active node
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int64_t i = b0 + j * kWave + lane;
+            v[j] = i < total ? cv.at_in((int32_t)i, slo, shi) : -1;
+            act |= (i < total ? 1u : 0u) << j;
+        }
+        if (TOPO) {
+            int32_t c0[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) c0[j] = v[j] >= 0 ? d.c[v[j]] : 1;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (c0[j] > 0) act &= ~(1u << j);
+        }
+        if (d.light_pull == kPushAll) {
+            uint64_t mk[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) mk[j] = act >> j & 1u ? d.mask[v[j]] : 0ull;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (act >> j & 1u) d.c[v[j]] = -__ffsll((unsigned long long)~mk[j]);
+            un.u[kUMapBytes] += 8 * __popc(act);
+            un.u[kUAssignNodes] += __popc(act);
+            continue;
+        }
+        Off b[K];
+        int32_t len[K], gb[K];
+        uint64_t used[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const bool a = act >> j & 1u;
+            b[j] = a ? d.rowptr[v[j]] : 0;
+            len[j] = a ? (int32_t)(d.rowptr[v[j] + 1] - b[j]) : 0;
+            gb[j] = a ? d.base(v[j]) : 0;
+            used[j] = 0;
+        }
+        for (int32_t q0 = 0;; q0 += C) {
+            int32_t cu[K][C];
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int q = 0; q < C; ++q) cu[j][q] = q0 + q < len[j] ? d.colidx[b[j] + q0 + q] + gb[j] : -1;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int q = 0; q < C; ++q) cu[j][q] = cu[j][q] >= 0 ? d.c[cu[j][q]] : 0;
+            bool more = false;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    const int32_t x = d.racy ? iabs(cu[j][q]) : cu[j][q];  // racy: in-flight tentatives too
+                    if (x > 0 && x <= 64) used[j] |= 1ull << (x - 1);
+                }
+                more |= q0 + C < len[j];
+            }
+            if (!more) break;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (!(act >> j & 1u)) continue;
+            d.c[v[j]] = -__ffsll((unsigned long long)~used[j]);
+            un.u[kUPullEntries] += len[j];
+        }
+        un.u[kUAssignNodes] += __popc(act);
+    }
+}
+
+// Conflict test, commit and push of the class-L items (Section II-C): v loses iff a smaller
+// neighbour holds its tentative color t.  Pull-only graphs scan the row up to v (sorted rows
+// stop there); push modes scan only the positions still pending, and drop from them the
+// neighbours found committed (their colors have reached v's mask).  Losers go to the
+// workgroup's class-L segment with one shared-memory atomic per wavefront (ballot and popcount
+// give each its slot); winners commit and, in push modes, set bit t - 1 (t <= 33) in their
+// neighbours' masks.
+template <bool TOPO, class D>
+__device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, int64_t seg_base, bool discard,
+                                               int32_t r, Units &un, int G, int32_t *list, int32_t seg_cap,
+                                               int *s_cnt, unsigned long long *s_deg) {
+    using Off = typename D::OffT;
+    constexpr int K = kLightK, C = kLightC;
+    const int lane = lane_id();
+    // blocks of 64 * K items go round the workgroups (block i to workgroup i mod G), so no
+    // workgroup takes more than total / G + 64 * K * (1 + 1/G) items: its out segments hold them
+    const int64_t gw = (int64_t)(threadIdx.x / kWave) * G + blockIdx.x;
+    const int64_t nw = (int64_t)G * (blockDim.x / kWave);
+    const int32_t total = cv.total;
+    const bool pull_only = d.light_pull == kPullOnly;
+    for (int64_t b0 = gw * (kWave * K); b0 < total; b0 += nw * (kWave * K)) {
+        int slo, shi;
+        cv.range((int32_t)b0, (int32_t)min<int64_t>(b0 + kWave * K, total) - 1, &slo, &shi);
+        int32_t v[K], t[K];
+        uint32_t act = 0;  // bit j: item j is an active node
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int64_t i = b0 + j * kWave + lane;
+            v[j] = i < total ? cv.at_in((int32_t)i, slo, shi) : -1;
+            act |= (i < total ? 1u : 0u) << j;
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] = v[j] >= 0 ? -d.c[v[j]] : 0;
+        if (TOPO) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (t[j] < 0) act &= ~(1u << j);  // committed (c > 0)
+        }
+        Off b[K];
+        int32_t len[K], gb[K];
+        uint32_t pm[K];  // pull-only: unused; push modes: pending positions not yet scanned
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const bool a = act >> j & 1u;
+            b[j] = a ? d.rowptr[v[j]] : 0;
+            len[j] = a ? (int32_t)(d.rowptr[v[j] + 1] - b[j]) : 0;
+            gb[j] = a ? d.base(v[j]) : 0;
+            pm[j] = a && !pull_only ? d.pend[v[j]] : 0u;
+        }
+        uint32_t lose = 0, done = ~act;  // bit j
+        uint32_t seen[K];                // push modes: positions found committed
+        int32_t read = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) seen[j] = 0;
+        for (int32_t q0 = 0;; q0 += C) {
+            int32_t pos[K][C], u[K][C];
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    if (pull_only) {
+                        pos[j][q] = !(done >> j & 1u) && q0 + q < len[j] ? q0 + q : -1;
+                    } else {
+                        pos[j][q] = !(done >> j & 1u) && pm[j] ? __ffs(pm[j]) - 1 : -1;
+                        pm[j] &= pm[j] - 1;
+                    }
+                }
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int q = 0; q < C; ++q) u[j][q] = pos[j][q] >= 0 ? d.colidx[b[j] + pos[j][q]] + gb[j] : INT32_MAX;
+            int32_t cu[K][C];
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int q = 0; q < C; ++q) cu[j][q] = u[j][q] < v[j] ? d.c[u[j][q]] : 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+#pragma unroll
+                for (int q = 0; q < C; ++q) {
+                    if (done >> j & 1u) continue;
+                    if (u[j][q] >= v[j]) {  // not a smaller neighbour; past the row's end if INT32_MAX
+                        if (d.sorted || u[j][q] == INT32_MAX) done |= 1u << j;
+                        continue;
+                    }
+                    ++read;
+                    if (iabs(cu[j][q]) == t[j]) {
+                        lose |= 1u << j;
+                        done |= 1u << j;
+                    }
+                    if (cu[j][q] > 0) seen[j] |= 1u << pos[j][q];
+                }
+                if (pull_only ? q0 + C >= len[j] : pm[j] == 0) done |= 1u << j;
+            }
+            if ((done & ((1u << K) - 1)) == (1u << K) - 1) break;
+        }
+        if (!pull_only) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (seen[j]) atomicAnd(&d.pend[v[j]], ~seen[j]);
+        }
+        // losers: one shared-memory atomic per wavefront for their slots, one for their degrees
+        lose &= act;
+        const uint32_t win = act & ~lose;
+        int nl = 0;
+        int64_t ldeg = 0;
+        uint64_t lm[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            lm[j] = __ballot(lose >> j & 1u);
+            nl += __popcll(lm[j]);
+            ldeg += lose >> j & 1u ? len[j] : 0;
+        }
+        if (nl) {
+            const int64_t dsum = wave_sum(ldeg);
+            int slot = 0;
+            if (lane == 0) {
+                slot = atomicAdd(&s_cnt[kL], nl);
+                atomicAdd(&s_deg[kL], (unsigned long long)dsum);
+            }
+            slot = __shfl(slot, 0);
+            if (slot + nl > seg_cap) {  // cannot happen (see above); reported instead of written
+                if (lane == 0) d.ct->seg_overflow = 1;
+                lose = 0;
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                if (lose >> j & 1u) {
+                    if (d.racy) d.c[v[j]] = 0;
+                    if (!discard) list[seg_base + slot + __popcll(lm[j] & lanes_below())] = v[j];
+                }
+                slot += __popcll(lm[j]);
+            }
+        }
+        // winners commit
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            if (!(win >> j & 1u)) continue;
+            d.c[v[j]] = t[j];
+            un.u[kUPushEntries] += pull_only ? 0 : len[j];
+        }
+        un.u[kUCommits] += __popc(win);
+        un.u[kUConflictNodes] += __popc(act);
+        un.u[kUConflictEntries] += read;
+        // push modes: bit t - 1 into every neighbour's color mask (t <= d + 1 <= 33), read first,
+        // the atomic only where the bit is missing
+        if (!pull_only && win) {
+            for (int32_t q0 = 0;; q0 += C) {
+                int32_t w[K][C];
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+#pragma unroll
+                    for (int q = 0; q < C; ++q)
+                        w[j][q] = (win >> j & 1u) && q0 + q < len[j] ? d.colidx[b[j] + q0 + q] + gb[j] : -1;
+                uint64_t mw[K][C];
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+#pragma unroll
+                    for (int q = 0; q < C; ++q) mw[j][q] = w[j][q] >= 0 ? d.mask[w[j][q]] : ~0ull;
+                bool more = false;
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const uint64_t bit = 1ull << ((t[j] - 1) & 63);
+#pragma unroll
+                    for (int q = 0; q < C; ++q)
+                        if (!(mw[j][q] & bit)) atomicOr((unsigned long long *)&d.mask[w[j][q]], (unsigned long long)bit);
+                    more |= (win >> j & 1u) && q0 + C < len[j];
+                }
+                if (!more) break;
+            }
+        }
+        if (d.grounds) {
+            // per item j: lanes committing nodes of the same graph as the first committing lane
+            // share one atomic
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const bool wj = win >> j & 1u;
+                const int32_t g = wj ? d.gidx[v[j]] : -1;
+                const uint64_t cm = __ballot(wj);
+                if (!cm) continue;
+                const int leader = __ffsll((unsigned long long)cm) - 1;
+                const int32_t g0 = __shfl(g, leader);
+                const uint64_t same = __ballot(wj && g == g0);
+                if (lane == leader) {
+                    atomicMax(&d.grounds[g0], r);
+                    if (d.gleft) atomicSub(&d.gleft[g0], (int32_t)__popcll(same));
+                }
+                if (wj && g != g0) {
+                    atomicMax(&d.grounds[g], r);
+                    if (d.gleft) atomicSub(&d.gleft[g], 1);
+                }
+            }
+        }
+    }
+}
+
 template <class D>
-__device__ void assign_step(const D &d, const RoundIn &in, Units &un, int G) {
+__device__ __forceinline__ void assign_step(const D &d, const RoundIn &in, Units &un, int G) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)G * blockDim.x;
     const int64_t gw = gt / kWave, nw = nt / kWave;
     const int lane = lane_id();
-    // class L: a thread per node; first zero bit of its color mask (pushed there by committed
-    // neighbours; d <= 32 neighbours leave a zero among the first 33 bits), or of a mask of
-    // its neighbours' committed colors read from their states (four loads in flight)
-    for (int64_t i = gt; i < in.cv[kL].total; i += nt) {
-        const int32_t v = in.cv[kL].at((int32_t)i);
-        const int32_t cv = d.c[v];
-        if (in.topo && cv > 0) continue;
-        if (d.light_pull == kPushAll) {
-            d.c[v] = -__ffsll((unsigned long long)~d.mask[v]);
-            un.u[kUMapBytes] += 8;
-        } else {
-            const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
-            const int32_t gb = d.base(v);
-            uint64_t used = 0;
-            for (int64_t k0 = b; k0 < e; k0 += 4) {
-                int32_t cu[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) cu[j] = k0 + j < e ? d.c[d.colidx[k0 + j] + gb] : 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int32_t x = d.racy ? iabs(cu[j]) : cu[j];  // racy: in-flight tentatives too
-                    if (x > 0 && x <= 64) used |= 1ull << (x - 1);
-                }
-            }
-            d.c[v] = -__ffsll((unsigned long long)~used);
-            un.u[kUPullEntries] += e - b;
-        }
-        un.u[kUAssignNodes] += 1;
-    }
+    // class L: a lane per node, several nodes in flight per lane
+    if (in.topo) light_assign<true>(d, in.cv[kL], un, G);
+    else light_assign<false>(d, in.cv[kL], un, G);
     // classes W and M.  Large rounds (at least four W/M nodes per wavefront): a thread per node
     // for the first zero bit of the color mask; nodes whose mask is full (64 colors taken) are
     // queued in shared memory and each gets a wavefront for its byte map from color 65 on (the
@@ -1113,7 +1541,7 @@ __device__ __forceinline__ void push_row_wave(const D &d, int64_t b, int64_t e, 
 // lanes of the group agree on every loop condition, and ballots are masked to
 // the group.  Quarter-wave groups read four chunks of 16 entries per pass.
 template <class D>
-__device__ bool ring_scan_group(const D &d, int32_t v, int32_t t, int wide, int S, Units &un) {
+__device__ __forceinline__ bool ring_scan_group(const D &d, int32_t v, int32_t t, int wide, int S, Units &un) {
     constexpr int kPass = 4;
     const int lane = lane_id(), gl = lane % S;
     const uint64_t gm = S == kWave ? ~0ull : (((1ull << S) - 1) << (lane - gl));
@@ -1174,7 +1602,7 @@ __device__ bool ring_scan_group(const D &d, int32_t v, int32_t t, int wide, int 
 // are placed through a shared counter per team, so their order in the ring
 // varies; the set, and with it every outcome, does not.
 template <class D>
-__device__ void conflict_wide_teams(const D &d, const RoundIn &in, const OutSegs &os, int32_t r, Units &un, int G, int T,
+__device__ __forceinline__ void conflict_wide_teams(const D &d, const RoundIn &in, const OutSegs &os, int32_t r, Units &un, int G, int T,
                                     bool discard, const int64_t (&seg_base)[kNumClasses], int *s_cnt,
                                     unsigned long long *s_deg) {
     constexpr int kPass = 4;
@@ -1281,7 +1709,7 @@ __device__ void conflict_wide_teams(const D &d, const RoundIn &in, const OutSegs
 }
 
 template <class D>
-__device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, int32_t r, Units &un, int G) {
+__device__ __forceinline__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, int32_t r, Units &un, int G) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)G * blockDim.x;
     const int64_t gw = gt / kWave, nw = nt / kWave;
     const int lane = lane_id();
@@ -1347,100 +1775,9 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
             }
         }
     }
-    // class L: a thread per node
-    for (int64_t i = gt; i < in.cv[kL].total; i += nt) {
-        const int32_t v = in.cv[kL].at((int32_t)i);
-        const int32_t cv = d.c[v];
-        if (in.topo && cv > 0) continue;
-        const int32_t t = -cv;
-        const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
-        const int32_t gb = d.base(v);
-        bool lose = false, done = false;
-        int32_t read = 0;
-        if (d.light_pull == kPullOnly) {
-            // four neighbours per step: their ids, then their states, then the test in row order
-            for (int64_t k0 = b; k0 < e && !lose && !done; k0 += 4) {
-                int32_t u[4], cu[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) u[j] = k0 + j < e ? d.colidx[k0 + j] + gb : INT32_MAX;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) cu[j] = u[j] < v ? d.c[u[j]] : 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (lose || done) continue;
-                    if (u[j] >= v) {
-                        if (d.sorted || u[j] == INT32_MAX) done = true;
-                        continue;
-                    }
-                    ++read;
-                    lose = iabs(cu[j]) == t;
-                }
-            }
-        } else {
-            // with pushes: only the row positions still pending (neighbours not seen committed;
-            // a committed neighbour's color has reached this node's mask), four per step, in
-            // row order; the committed ones seen now leave the set
-            const uint32_t p0 = d.pend[v];
-            uint32_t pm = p0, seen = 0;
-            while (pm && !lose && !done) {
-                int32_t jj[4], u[4], cu[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    jj[j] = pm ? __ffs(pm) - 1 : -1;
-                    pm &= pm - 1;
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j) u[j] = jj[j] >= 0 ? d.colidx[b + jj[j]] + gb : INT32_MAX;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) cu[j] = u[j] < v ? d.c[u[j]] : 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (lose || done) continue;
-                    if (u[j] >= v) {
-                        if (d.sorted || u[j] == INT32_MAX) done = true;
-                        continue;
-                    }
-                    ++read;
-                    lose = iabs(cu[j]) == t;
-                    if (cu[j] > 0) seen |= 1u << jj[j];
-                }
-            }
-            if (seen) d.pend[v] = p0 & ~seen;
-        }
-        un.u[kUConflictNodes] += 1;
-        un.u[kUConflictEntries] += read;
-        if (lose) {
-            if (d.racy) d.c[v] = 0;
-            const int p = atomicAdd(&s_cnt[kL], 1);
-            atomicAdd(&s_deg[kL], (unsigned long long)(e - b));
-            if (!discard) os.list[seg_base[kL] + p] = v;
-        } else {
-            d.c[v] = t;
-            un.u[kUCommits] += 1;
-            // a thread's own row, four entries at a time (the row-push rules above)
-            if (d.light_pull != kPullOnly) push_row(d, b, e, t, gb, d.fshift(v), 0, 1);
-            un.u[kUPushEntries] += d.light_pull == kPullOnly ? 0 : e - b;
-        }
-        if (d.grounds) {
-            // lanes committing nodes of the same graph as the first committing lane share one atomic
-            const bool com = !lose;
-            const int32_t g = com ? d.gidx[v] : -1;
-            const uint64_t cm = __ballot(com);
-            if (cm) {
-                const int leader = __ffsll((unsigned long long)cm) - 1;
-                const int32_t gl = __shfl(g, leader);
-                const uint64_t same = __ballot(com && g == gl);
-                if (lane == leader) {
-                    atomicMax(&d.grounds[gl], r);
-                    if (d.gleft) atomicSub(&d.gleft[gl], (int32_t)__popcll(same));
-                }
-                if (com && g != gl) {
-                    atomicMax(&d.grounds[g], r);
-                    if (d.gleft) atomicSub(&d.gleft[g], 1);
-                }
-            }
-        }
-    }
+    // class L: a lane per node, several nodes in flight per lane
+    if (in.topo) light_conflict<true>(d, in.cv[kL], seg_base[kL], discard, r, un, G, os.list, os.cap[kL], s_cnt, s_deg);
+    else light_conflict<false>(d, in.cv[kL], seg_base[kL], discard, r, un, G, os.list, os.cap[kL], s_cnt, s_deg);
     __syncthreads();
     if (threadIdx.x < kNumClasses) {
         os.cnt[threadIdx.x * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
@@ -1454,7 +1791,7 @@ __device__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, 
 // kRoundBlock hubs at a time (row bounds, color, chunk prefix sums) in shared
 // memory; wavefront w then takes chunks w, w + nw, ... of the staged batch.
 template <class D>
-__device__ void hub_push_step(const D &d, int32_t nwon, Units &un, int G) {
+__device__ __forceinline__ void hub_push_step(const D &d, int32_t nwon, Units &un, int G) {
     constexpr int kChunk = 4 * kWave;
     __shared__ int64_t s_b[kRoundBlock], s_e[kRoundBlock], s_fsh[kRoundBlock];
     __shared__ int32_t s_t[kRoundBlock], s_base[kRoundBlock], s_pre[kRoundBlock + 1];
@@ -1499,7 +1836,7 @@ __device__ void hub_push_step(const D &d, int32_t nwon, Units &un, int G) {
 // Round bookkeeping by workgroup 0 (all its threads): trace, work units, and
 // the stop test (a round that starts with an empty worklist is not run).
 template <class D>
-__device__ void round_record(const D &d, int r, const RoundIn &in, bool reset_hubs, int writers) {
+__device__ __forceinline__ void round_record(const D &d, int r, const RoundIn &in, bool reset_hubs, int writers) {
     __shared__ unsigned long long s_deg[kNumClasses];
     if (in.total == 0) {
         if (threadIdx.x == 0) {
@@ -1538,7 +1875,7 @@ __device__ void round_record(const D &d, int r, const RoundIn &in, bool reset_hu
 }
 
 template <class D>
-__device__ OutSegs out_segs(const D &d, int r) {
+__device__ __forceinline__ OutSegs out_segs(const D &d, int r) {
     OutSegs os;
     const int dst = (r + 1) & 1;  // round r writes the list round r+1 reads
     os.list = d.seg_list[dst];
@@ -1561,7 +1898,7 @@ __device__ __forceinline__ void tick(const D &d, int64_t i) {
 // [b*span_k, (b+1)*span_k) of class k and appends its uncolored nodes, in
 // order, to its own segment.
 template <class D>
-__device__ void rebuild_step(const D &d, int par, int G) {
+__device__ __forceinline__ void rebuild_step(const D &d, int par, int G) {
     __shared__ int s_cnt;
     __shared__ unsigned long long s_deg;
     const int b = blockIdx.x, nb = G, stride = gridDim.x;

@@ -647,6 +647,7 @@ int Server::step() {
             return fail(IPGC_EHIP, "a grid-barrier wait exceeded %d ms: not every workgroup of the cooperative launch "
                         "ran (%d workgroups)", P.barrier_ms, grid);
     }
+    if (host_ct->seg_overflow) return fail(IPGC_EHIP, "internal error: a worklist segment overflowed");
     const int32_t ran_to = host_ct->finished ? host_ct->rounds : last;
     st.rounds += ran_to - first + 1;
     st.steps += 1;
