@@ -6,19 +6,23 @@
 // The device code and its data layout are described in ipgc_device.hpp.
 //
 // One call: check the CSR ends, then (one stream, in order)
-//   k_init        initial state, node classes, row-pointer checks, class counts
+//   k_init        initial state, node classes, row-pointer checks, class counts;
+//                 column ids in range and sorted rows of the light nodes
+//                 (unless validation is off)
 //   k_offsets     prefix sums of the class counts, list layouts
-//   k_fill_static every node grouped by class, ascending ids
-//   k_check_light column ids in range and sorted rows, light rows (unless
-//                 validation is off)
-//   k_prep_wide   smaller-neighbour rings of W/M nodes, with the same checks
-//                 of their rows
+//   k_fill_static every node grouped by class, ascending ids (not written when
+//                 one class holds every node); the state pushes need
+//   k_prep_wide   smaller-neighbour rings of W nodes, with the same checks of
+//                 their rows
+//   k_prep_hubs   the same for class-M nodes, a row chunk per wavefront (a
+//                 counting launch, then a placing launch)
 //   k_rounds      every round, one cooperative launch with grid barriers
 //                 (or k_assign_round + k_conflict_round + k_push_round per
 //                 round when stepped)
-// and read back the round count.  The host synchronizes after the row-pointer
-// checks (rows are only read through valid pointers), after the column checks
-// (their verdict decides whether to go on) and after the rounds.
+// and read back the round count.  The host synchronizes after k_fill_static
+// (class counts decide the launches that follow; a node's row is only read
+// through its own checked row pointers), after the ring building (the column
+// checks decide whether to go on) and after the rounds.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -424,27 +428,19 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
     TRY(clear(ws.units.p, sizeof(int64_t) * kNumUnits * grid, s));
     TRY(clear(ws.F.p, (size_t)(m + n + 64), s));  // every byte map starts empty
     TRY(pf.begin(kKindInit));
-    k_init<<<prep_grid, kPrepBlock, 0, s>>>(d, ws.cls.p, (int32_t)span);
+    k_init<<<prep_grid, kPrepBlock, 0, s>>>(d, ws.cls.p, (int32_t)span, P.check_ids ? 1 : 0);
     k_offsets<<<1, 1024, 0, s>>>(d, prep_grid);
-    k_fill_static<<<prep_grid, kPrepBlock, 0, s>>>(d, (int32_t)span);
+    k_fill_static<<<prep_grid, kPrepBlock, 0, s>>>(d, (int32_t)span, P.light);
     TRY(pf.end(kKindInit));
     HIP_TRY(hipGetLastError());
-    // the column checks read rows through rowptr, so they only run on row pointers that passed
     TRY(read_counters(ws, s));
     if (ws.host_ct->bad_rows) return fail(IPGC_EBADCSR, "rowptr is decreasing or outside [0, m]");
-    const int64_t n_light = ws.host_ct->class_n[kL];
     const int64_t n_wide = (int64_t)ws.host_ct->class_n[kW] + ws.host_ct->class_n[kM];
     if (P.light == 0 || (P.light < 0 && n_wide > 0)) d.light_pull = kPushAll;
     else d.light_pull = n_wide > 0 ? kPullLight : kPullOnly;
     d.racy = P.racy ? 1 : 0;
     d.tail_groups = P.tail_groups;
     d.discard = P.mode == IPGC_MODE_REBUILD ? 1 : 0;
-    if (P.check_ids && n_light > 0) {
-        TRY(pf.begin(kKindCheck));
-        k_check_light<<<(int)((n_light + kPrepBlock - 1) / kPrepBlock), kPrepBlock, 0, s>>>(d);  // a node per thread
-        TRY(pf.end(kKindCheck));
-        HIP_TRY(hipGetLastError());
-    }
     if (n_wide > 0) {  // also checks the ids of the wide rows
         const int64_t n_w = ws.host_ct->class_n[kW], n_hub = ws.host_ct->class_n[kM];
         const int64_t hub_chunks = ws.host_ct->hub_chunks;

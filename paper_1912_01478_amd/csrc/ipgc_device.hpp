@@ -139,6 +139,7 @@ struct Counters {
     int32_t bad_full;                 // IPGC_VALIDATE_FULL: bit 0 self-loop, bit 1 duplicate, bit 2 no reverse entry
     int32_t seg_overflow;             // a workgroup had more losers than its out segment holds (never expected)
     int32_t hub_chunks;               // row chunks of kRingChunk entries over all class-M nodes
+    int32_t static_ident;             // class L or W holds every node: its static list is 0, 1, ..., n-1 (not written)
 };
 
 // A committed hub waiting for the push step.
@@ -465,30 +466,51 @@ __device__ __forceinline__ int block_append(bool flag, int *count) {
 // the worklist), classes, byte-map metadata, row-pointer checks, and the class
 // counts of each workgroup's node range.  Workgroup b covers nodes
 // [b*span, (b+1)*span).
+//
+// With `check`, the rows of class L are checked here too (ids inside the node's
+// graph, strictly ascending), four entries at a time; a row is read only if its
+// own bounds are valid.  Rows of classes W and M are checked while their rings
+// are built.
 template <class D>
-__global__ __launch_bounds__(kPrepBlock) void k_init(D d, int8_t *cls, int32_t span) {
+__global__ __launch_bounds__(kPrepBlock) void k_init(D d, int8_t *cls, int32_t span, int32_t check) {
     const int64_t lo = (int64_t)blockIdx.x * span, hi = std::min<int64_t>(lo + span, d.n);
     int cnt[kNumClasses] = {0, 0, 0};
     int64_t deg[kNumClasses] = {0, 0, 0};
     int chunks = 0;  // row chunks of class-M nodes (their rings are built a chunk per wavefront)
-    int bad = 0;
+    int bad = 0, bad_id = 0, unsorted = 0;
     for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
         // Round 1 assigns color 1 to every node (no neighbour is committed yet), so the state
         // starts there: tentative color 1, and round 1 skips its assign step.
         d.c[v] = -1;
-        d.mask[v] = 0;
         const int64_t a = d.rowptr[v], e = d.rowptr[v + 1];
         const bool b = a < 0 || e < a || e > d.m || e - a >= INT32_MAX;
         bad |= b;
         const int64_t dv = b ? 0 : e - a;
         const int k = node_class(dv, d.light_max, d.hub_min);
         cls[v] = (int8_t)k;
-        d.pend[v] = k != kL ? 0u : dv >= 32 ? ~0u : (1u << dv) - 1u;
         cnt[k] += 1;
         deg[k] += dv;
         if (k == kM) chunks += (int)((dv + kRingChunk - 1) / kRingChunk);
+        if (check && k == kL && dv > 0) {
+            const int64_t glo = d.base((int32_t)v), ghi = d.id_end((int32_t)v);
+            int64_t prev = -1;
+            for (int64_t k0 = a; k0 < e; k0 += 4) {
+                int64_t u[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) u[j] = k0 + j < e ? (int64_t)d.colidx[k0 + j] + glo : INT64_MAX;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (k0 + j >= e) continue;
+                    bad_id |= (u[j] < glo || u[j] >= ghi);
+                    unsorted |= (u[j] <= prev);
+                    prev = u[j];
+                }
+            }
+        }
     }
     if (__ballot(bad) && lane_id() == 0) d.ct->bad_rows = 1;
+    if (__ballot(bad_id) && lane_id() == 0) d.ct->bad_ids = 1;
+    if (__ballot(unsorted) && lane_id() == 0) d.ct->unsorted = 1;
     __shared__ int s_cnt[kNumClasses + 1];
     __shared__ unsigned long long s_deg[kNumClasses];
     if (threadIdx.x <= kNumClasses) s_cnt[threadIdx.x] = 0;
@@ -567,6 +589,7 @@ __global__ __launch_bounds__(1024) void k_offsets(D d, int32_t prep_grid) {
         }
         d.ct->static_off[kNumClasses] = d.n;
         d.ct->seg_off[kNumClasses] = so;
+        d.ct->static_ident = d.n > 0 && (d.ct->class_n[kL] == d.n || d.ct->class_n[kW] == d.n);
         if (d.hub_pre) d.hub_pre[d.ct->class_n[kM]] = d.ct->hub_chunks;
     }
 }
@@ -574,9 +597,21 @@ __global__ __launch_bounds__(1024) void k_offsets(D d, int32_t prep_grid) {
 // The static list: every node grouped by class, ascending id within a class.
 // For class-M nodes also the first of their row chunks (hub_pre, in the same
 // order), for k_prep_hubs.
+//
+// Also the state that only pushes use (light_mode 0: pushes forced; or any node
+// of class W/M, which receive pushes): empty color masks and, for class L, every
+// row position pending.
 template <class D>
-__global__ __launch_bounds__(kPrepBlock) void k_fill_static(D d, int32_t span) {
+__global__ __launch_bounds__(kPrepBlock) void k_fill_static(D d, int32_t span, int32_t light_mode) {
     const int64_t lo = (int64_t)blockIdx.x * span, hi = std::min<int64_t>(lo + span, d.n);
+    if (light_mode == 0 || d.ct->class_n[kW] + d.ct->class_n[kM] > 0) {
+        for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+            d.mask[v] = 0;
+            const int64_t dv = d.rowptr[v + 1] - d.rowptr[v];  // checked by k_init before any use
+            d.pend[v] = d.cls[v] != kL ? 0u : dv >= 32 ? ~0u : (1u << dv) - 1u;
+        }
+    }
+    if (d.ct->static_ident) return;
     int32_t base[kNumClasses];
     for (int k = 0; k < kNumClasses; ++k) base[k] = d.block_cnt[k * gridDim.x + blockIdx.x];
     int32_t cbase = d.block_cnt[kNumClasses * gridDim.x + blockIdx.x];  // this workgroup's first chunk
@@ -600,37 +635,6 @@ __global__ __launch_bounds__(kPrepBlock) void k_fill_static(D d, int32_t span) {
             base[q] += tot;
         }
     }
-}
-
-// Column checks of light rows (a thread each, four independent loads in
-// flight): ids inside [0, n) and strictly ascending rows.  Wider rows are
-// checked by k_prep_wide while it reads them.
-template <class D>
-__global__ __launch_bounds__(kPrepBlock) void k_check_light(D d) {
-    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
-    int bad = 0, unsorted = 0;
-    const int32_t nL = d.ct->class_n[kL];
-    const int32_t *listL = d.static_list + d.ct->static_off[kL];
-    for (int64_t i = gt; i < nL; i += nt) {
-        const int32_t v = listL[i];
-        const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
-        const int64_t lo = d.base(v), hi = d.id_end(v);
-        int64_t prev = -1;
-        for (int64_t k0 = b; k0 < e; k0 += 4) {
-            int64_t u[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) u[j] = k0 + j < e ? (int64_t)d.colidx[k0 + j] + lo : INT64_MAX;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (k0 + j >= e) continue;
-                bad |= (u[j] < lo || u[j] >= hi);
-                unsorted |= (u[j] <= prev);
-                prev = u[j];
-            }
-        }
-    }
-    if (__ballot(bad) && lane_id() == 0) d.ct->bad_ids = 1;
-    if (__ballot(unsorted) && lane_id() == 0) d.ct->unsorted = 1;
 }
 
 // Ring of W/M node v, built by one wavefront in one pass over its row, which
@@ -676,6 +680,14 @@ __device__ void ring_build_wave(const D &d, int32_t v, int64_t lo, int64_t hi, i
     }
 }
 
+// Node at position i of class k's static list (0, 1, ..., n-1 when one class
+// holds every node and the list is not written).
+template <class D>
+__device__ __forceinline__ int32_t static_at(const D &d, int k, int64_t i) {
+    const int64_t p = d.ct->static_off[k] + i;
+    return d.ct->static_ident ? (int32_t)p : d.static_list[p];
+}
+
 // Rings of the class-W nodes (a wavefront each; with hub_pre unset, of the
 // class-M nodes too), with the checks of their rows.
 template <class D>
@@ -683,10 +695,9 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep_wide(D d) {
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
     const int32_t nWide = d.ct->class_n[kW] + (d.hub_pre ? 0 : d.ct->class_n[kM]);
-    const int32_t *listWide = d.static_list + d.ct->static_off[kW];
     int bad = 0, unsorted = 0;
     for (int64_t i = gw; i < nWide; i += nw) {
-        const int32_t v = listWide[i];
+        const int32_t v = static_at(d, kW, i);
         ring_build_wave(d, v, d.base(v), d.id_end(v), bad, unsorted);
     }
     if (__ballot(bad) && lane_id() == 0) d.ct->bad_ids = 1;
@@ -938,7 +949,8 @@ static __global__ __launch_bounds__(kPrepBlock) void k_batch_union(const int64_t
 // topology-driven sweep, or round 1) or the segmented list of the previous
 // round, read through the prefix sums of its segment counts.
 struct ClassView {
-    const int32_t *base;  // static: first entry of the class; segmented: first segment of the class
+    const int32_t *base;  // static: first entry of the class (null: the list 0, 1, ..., n-1); segmented:
+                          // first segment of the class
     const int32_t *pre;   // segmented: shared-memory prefix sums (grid + 1 entries), else null
     int32_t cap;          // segmented: entries per segment
     int32_t total;
@@ -955,7 +967,7 @@ struct ClassView {
 
     // item i, found among segments [lo, hi) (see range)
     __device__ __forceinline__ int32_t at_in(int32_t i, int lo, int hi) const {
-        if (!pre) return base[i];
+        if (!pre) return base ? base[i] : i;  // null base: the static list 0, 1, ..., n-1
         const int s = seg_of(i, lo, hi);
         return base[(int64_t)s * cap + (i - pre[s])];
     }
@@ -1016,7 +1028,7 @@ __device__ __forceinline__ RoundIn round_view(const D &d, int r, int32_t (*pre)[
     const int src = r & 1;  // round r reads list (r & 1) written by round r-1
     for (int k = 0; k < kNumClasses; ++k) {
         if (r == 1 || in.topo) {
-            in.cv[k].base = d.static_list + d.ct->static_off[k];
+            in.cv[k].base = d.ct->static_ident ? nullptr : d.static_list + d.ct->static_off[k];
             in.cv[k].pre = nullptr;
             in.cv[k].cap = 0;
             in.cv[k].total = d.ct->class_n[k];
@@ -1909,12 +1921,13 @@ __device__ __forceinline__ void rebuild_step(const D &d, int par, int G) {
         }
         __syncthreads();
         const int32_t total = d.ct->class_n[k];
+        const bool ident = d.ct->static_ident;
         const int32_t *list = d.static_list + d.ct->static_off[k];
         const int64_t span = ((int64_t)total + nb - 1) / nb, lo = (int64_t)b * span, hi = min<int64_t>(lo + span, total);
         int32_t *seg = d.seg_list[par] + d.ct->seg_off[k] + (int64_t)b * d.ct->seg_cap[k];  // segment b of class k
         for (int64_t c0 = lo; c0 < hi; c0 += blockDim.x) {
             const int64_t i = c0 + threadIdx.x;
-            const int32_t v = i < hi ? list[i] : 0;
+            const int32_t v = i >= hi ? 0 : ident ? (int32_t)(d.ct->static_off[k] + i) : list[i];
             const bool act = i < hi && d.c[v] <= 0;
             const int64_t ds = wave_sum(act ? d.rowptr[v + 1] - d.rowptr[v] : 0);
             if (lane_id() == 0 && ds) atomicAdd(&s_deg, (unsigned long long)ds);
