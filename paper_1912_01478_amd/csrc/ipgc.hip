@@ -132,7 +132,7 @@ struct Workspace {
         // class-M nodes (degree above hub_min) + the total; two counts per row chunk of them
         const int64_t hubs = std::min<int64_t>(n, m / ((int64_t)hub_min + 1));
         TRY(f(hub_pre, hubs + 1));
-        TRY(f(hub_cnt, 2 * (hubs + m / kRingChunk + 1)));
+        TRY(f(hub_cnt, hubs + m / kRingChunk + 1));
         TRY(f(block_deg, (int64_t)kNumClasses * prep_grid));
         TRY(f(units, (int64_t)kNumUnits * kMaxRoundBlocks));
         TRY(f(trace, n));

@@ -181,7 +181,7 @@ struct DevT {
     int32_t *block_cnt;      // [kNumClasses + 1][prep grid] class counts (then class-M row chunks) per
                              // preparation workgroup
     int32_t *hub_pre;        // class-M nodes in static-list order: first row chunk of each (+ the total)
-    int32_t *hub_cnt;        // per row chunk of a class-M node: its smaller neighbours of class L, of class W/M
+    int32_t *hub_cnt;        // per row chunk of a class-M node: its smaller neighbours
     int64_t *block_deg;      // [kNumClasses][prep grid]
     int64_t *units;          // [kNumUnits][grid] work counters per round workgroup
     Counters *ct;
@@ -637,46 +637,63 @@ __global__ __launch_bounds__(kPrepBlock) void k_fill_static(D d, int32_t span, i
     }
 }
 
+// Ring building reads P chunks of 64 row entries per step, so that P loads are
+// in flight together.
+constexpr int kRingPass = 4;
+
+// Row entries k0 + j * 64 + lane (j < P) below k1, of node v whose row ends at
+// e: u[j] the entry's id, sel[j] whether it is a smaller neighbour (a ring
+// entry).  With check, ids outside [lo, hi) set bad (such an id is never
+// selected) and an entry not above its predecessor sets unsorted.
+template <int P, class D>
+__device__ __forceinline__ void ring_select(const D &d, int32_t v, int64_t k0, int64_t k1, int64_t e, int64_t lo,
+                                            int64_t hi, bool (&sel)[P], int32_t (&u)[P], int &bad, int &unsorted,
+                                            bool check) {
+    const int lane = lane_id();
+    int64_t ug[P], nx[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const int64_t k = k0 + j * kWave + lane;
+        ug[j] = k < k1 ? (int64_t)d.colidx[k] + lo : -1;
+        nx[j] = check && k < k1 && k + 1 < e ? (int64_t)d.colidx[k + 1] + lo : INT64_MAX;
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const int64_t k = k0 + j * kWave + lane;
+        const bool ok = ug[j] >= lo && ug[j] < hi;
+        if (check && k < k1) {
+            bad |= !ok;
+            unsorted |= nx[j] <= ug[j];
+        }
+        u[j] = (int32_t)ug[j];
+        sel[j] = ok && u[j] < v;
+    }
+}
+
 // Ring of W/M node v, built by one wavefront in one pass over its row, which
-// it also checks (ids inside [lo, hi), strictly ascending).  Within the node's
-// region [0, d), smaller neighbours of class L are written upward from position
-// 0 and those of class W or M downward from position d - 1 and then reversed,
-// so the ring starts at the W/M part and wraps around into the L part, both in
-// ascending id order: neighbours of high degree come first in every scan.
+// it also checks (ids inside [lo, hi), strictly ascending): the node's smaller
+// neighbours in row order, from position 0 of its region [0, d).  (Putting the
+// neighbours of class W/M first, which stay uncolored longest, made the rounds
+// no faster and cost a class lookup per entry.)
 template <class D>
 __device__ void ring_build_wave(const D &d, int32_t v, int64_t lo, int64_t hi, int &bad, int &unsorted) {
-    const int lane = lane_id();
     const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
-    const int32_t cap = (int32_t)(e - b);
-    int32_t nl = 0, nh = 0;  // smaller neighbours of class L / of class W or M written so far
-    for (int64_t k0 = b; k0 < e; k0 += kWave) {
-        const int64_t k = k0 + lane;
-        int q = -1;
-        int32_t u = -1;
-        if (k < e) {
-            const int64_t ug = (int64_t)d.colidx[k] + lo;
-            const bool ok = ug >= lo && ug < hi;
-            bad |= !ok;
-            if (k + 1 < e) unsorted |= ((int64_t)d.colidx[k + 1] + lo <= ug);
-            u = (int32_t)ug;
-            if (ok && u < v) q = d.cls[u] == kL ? 0 : 1;
+    int32_t nl = 0;  // smaller neighbours written so far
+    constexpr int P = kRingPass;
+    for (int64_t k0 = b; k0 < e; k0 += P * kWave) {
+        bool sel[P];
+        int32_t u[P];
+        ring_select<P>(d, v, k0, e, e, lo, hi, sel, u, bad, unsorted, true);
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const uint64_t m = __ballot(sel[j]);
+            if (sel[j]) d.lower[b + nl + __popcll(m & lanes_below())] = u[j];
+            nl += __popcll(m);
         }
-        const uint64_t m0 = __ballot(q == 0), m1 = __ballot(q == 1);
-        if (q == 0) d.lower[b + nl + __popcll(m0 & lanes_below())] = u;
-        if (q == 1) d.lower[b + cap - 1 - (nh + __popcll(m1 & lanes_below()))] = u;
-        nl += __popcll(m0);
-        nh += __popcll(m1);
     }
-    // the W/M part was written downward; reverse it so both parts run in ascending id order
-    int32_t *wm = d.lower + b + cap - nh;
-    for (int32_t j = lane; j < nh / 2; j += kWave) {
-        const int32_t x = wm[j], y = wm[nh - 1 - j];
-        wm[j] = y;
-        wm[nh - 1 - j] = x;
-    }
-    if (lane == 0) {
-        d.lstart[v] = nh > 0 ? cap - nh : 0;
-        d.llen[v] = nl + nh;
+    if (lane_id() == 0) {
+        d.lstart[v] = 0;
+        d.llen[v] = nl;
     }
 }
 
@@ -706,57 +723,41 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep_wide(D d) {
 
 // Part of class-M node v's ring from row entries [k0, k1) of its row [b, e),
 // by one wavefront.  Counting pass (WRITE false): the chunk's smaller
-// neighbours of class L (*nl) and of class W/M (*nh), with the checks of its
-// entries.  Writing pass: the same neighbours, in row order, at ring positions
-// posL.. (class L, from position 0 of the node's region upward) and posH..
-// (class W/M, in [d - NH, d) for NH of them over the whole row), so the ring is
-// laid out exactly as ring_build_wave lays it out.
+// neighbours (returned), with the checks of its entries.  Placing pass: the same
+// neighbours, in row order, at ring positions pos.., so that the ring is laid
+// out exactly as ring_build_wave lays it out.
 template <bool WRITE, class D>
-__device__ void ring_build_chunk(const D &d, int32_t v, int64_t b, int64_t e, int64_t k0, int64_t k1, int64_t lo,
-                                 int64_t hi, int32_t posL, int32_t posH, int &bad, int &unsorted, int32_t *nl_out,
-                                 int32_t *nh_out) {
-    const int lane = lane_id();
-    int32_t nl = 0, nh = 0;
-    for (int64_t p = k0; p < k1; p += kWave) {
-        const int64_t k = p + lane;
-        int q = -1;
-        int32_t u = -1;
-        if (k < k1) {
-            const int64_t ug = (int64_t)d.colidx[k] + lo;
-            const bool ok = ug >= lo && ug < hi;
-            if (!WRITE) {
-                bad |= !ok;
-                if (k + 1 < e) unsorted |= ((int64_t)d.colidx[k + 1] + lo <= ug);
-            }
-            u = (int32_t)ug;
-            if (ok && u < v) q = d.cls[u] == kL ? 0 : 1;
+__device__ int32_t ring_build_chunk(const D &d, int32_t v, int64_t b, int64_t e, int64_t k0, int64_t k1, int64_t lo,
+                                    int64_t hi, int32_t pos, int &bad, int &unsorted) {
+    int32_t nl = 0;
+    constexpr int P = kRingPass;
+    for (int64_t p = k0; p < k1; p += P * kWave) {
+        bool sel[P];
+        int32_t u[P];
+        ring_select<P>(d, v, p, k1, e, lo, hi, sel, u, bad, unsorted, !WRITE);
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const uint64_t m = __ballot(sel[j]);
+            if (WRITE && sel[j]) d.lower[b + pos + nl + __popcll(m & lanes_below())] = u[j];
+            nl += __popcll(m);
         }
-        const uint64_t m0 = __ballot(q == 0), m1 = __ballot(q == 1);
-        if (WRITE) {
-            if (q == 0) d.lower[b + posL + nl + __popcll(m0 & lanes_below())] = u;
-            if (q == 1) d.lower[b + posH + nh + __popcll(m1 & lanes_below())] = u;
-        }
-        nl += __popcll(m0);
-        nh += __popcll(m1);
     }
-    *nl_out = nl;
-    *nh_out = nh;
+    return nl;
 }
 
 // Rings of the class-M nodes: their rows are cut into chunks of kRingChunk
 // entries (hub_pre: first chunk of each node, in static-list order), and
 // wavefront w of the grid takes chunks w, w + waves, ...; a node of degree 10^5
 // costs about as much as fifty of degree 2048 instead of one wavefront walking
-// its whole row.  Two launches: WRITE false counts each chunk's parts into
-// hub_cnt and checks the entries; WRITE true places them from the prefix of
-// the node's chunk counts and sets the ring's start and length.
+// its whole row.  Two launches: WRITE false counts each chunk's smaller
+// neighbours into hub_cnt and checks the entries; WRITE true places them from
+// the prefix of the node's chunk counts and sets the ring's start and length.
 template <bool WRITE, class D>
 __global__ __launch_bounds__(kPrepBlock) void k_prep_hubs(D d) {
     const int lane = lane_id();
     const int64_t gw = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
     const int32_t nM = d.ct->class_n[kM];
-    const int32_t *listM = d.static_list + d.ct->static_off[kM];
     const int32_t total = d.hub_pre[nM];
     int bad = 0, unsorted = 0;
     for (int64_t g = gw; g < total; g += nw) {
@@ -769,36 +770,26 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep_hubs(D d) {
             lo += (int64_t)(63 - __clzll((unsigned long long)le)) * step;
             hi = min(hi, lo + step);
         }
-        const int32_t v = listM[lo];
+        const int32_t v = static_at(d, kM, lo);
         const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
         const int32_t c0 = d.hub_pre[lo], c1 = d.hub_pre[lo + 1];
         const int64_t k0 = b + (g - c0) * (int64_t)kRingChunk, k1 = min<int64_t>(k0 + kRingChunk, e);
-        int32_t nl, nh;
         if (!WRITE) {
-            ring_build_chunk<false>(d, v, b, e, k0, k1, d.base(v), d.id_end(v), 0, 0, bad, unsorted, &nl, &nh);
-            if (lane == 0) {
-                d.hub_cnt[2 * g] = nl;
-                d.hub_cnt[2 * g + 1] = nh;
-            }
+            const int32_t nl = ring_build_chunk<false>(d, v, b, e, k0, k1, d.base(v), d.id_end(v), 0, bad, unsorted);
+            if (lane == 0) d.hub_cnt[g] = nl;
         } else {
-            int64_t bl = 0, bh = 0, tl = 0, th = 0;  // this node's chunks before g, and all of them
+            int64_t before = 0, all = 0;  // this node's chunks before g, and all of them
             for (int64_t c = c0 + lane; c < c1; c += kWave) {
-                const int32_t x = d.hub_cnt[2 * c], y = d.hub_cnt[2 * c + 1];
-                bl += c < g ? x : 0;
-                bh += c < g ? y : 0;
-                tl += x;
-                th += y;
+                const int32_t x = d.hub_cnt[c];
+                before += c < g ? x : 0;
+                all += x;
             }
-            bl = wave_sum(bl);
-            bh = wave_sum(bh);
-            tl = wave_sum(tl);
-            th = wave_sum(th);
-            const int32_t cap = (int32_t)(e - b);
-            ring_build_chunk<true>(d, v, b, e, k0, k1, d.base(v), d.id_end(v), (int32_t)bl,
-                                   (int32_t)(cap - th + bh), bad, unsorted, &nl, &nh);
+            before = wave_sum(before);
+            all = wave_sum(all);
+            ring_build_chunk<true>(d, v, b, e, k0, k1, d.base(v), d.id_end(v), (int32_t)before, bad, unsorted);
             if (g == c0 && lane == 0) {
-                d.lstart[v] = th > 0 ? (int32_t)(cap - th) : 0;
-                d.llen[v] = (int32_t)(tl + th);
+                d.lstart[v] = 0;
+                d.llen[v] = (int32_t)all;
             }
         }
     }
