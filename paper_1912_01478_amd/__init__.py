@@ -445,11 +445,13 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
                          light_max_degree: int = 0, hub_min_degree: int = 0, validate: int = VALIDATE_DEFAULT,
                          stepped: bool = False, out=None, stream=None, trace: bool = False,
                          profile_mask: int = 0, workgroups: int = 0, light: str = "auto",
-                         racy: bool = False, tail_workgroups: int = 0, barrier_timeout_ms: int = 0) -> BatchColoring:
+                         racy: bool = False, tail_workgroups: int = 0, barrier_timeout_ms: int = 0,
+                         timeline: int = 0) -> BatchColoring:
     """Color many graphs in one launch.  ``rowptr_packed`` (int32[N+G]) and ``colidx_packed``
     (int32[M]) are device tensors in the layout of ``pack_graphs``; ``node_off`` and ``edge_off``
     (G+1 int64 each) are host arrays.  Each graph gets the coloring and round count it gets alone.
-    ``trace`` and ``profile_mask`` are as for ``color_graph``, over the rounds of the whole batch."""
+    ``trace``, ``profile_mask`` and ``timeline`` are as for ``color_graph``, over the rounds of the
+    whole batch."""
     import numpy as np
     import torch
 
@@ -472,8 +474,8 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
         out = torch.empty(N, dtype=torch.int32, device=dev)
     elif out.dtype != torch.int32 or out.numel() != N or not out.is_contiguous() or out.device != dev:
         raise ValueError("out must be a contiguous int32 tensor of N entries on the batch's device")
-    call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, N, profile_mask, 0, workgroups,
-                 light, racy, tail_workgroups, barrier_timeout_ms)
+    call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, N, profile_mask, timeline,
+                 workgroups, light, racy, tail_workgroups, barrier_timeout_ms)
     rounds = np.full(max(G, 1), -1, dtype=np.int32)
     if stream is None:
         stream = torch.cuda.current_stream(dev)

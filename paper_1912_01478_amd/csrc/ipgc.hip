@@ -320,6 +320,15 @@ int full_check_verdict(int bits) {
     return IPGC_OK;
 }
 
+// IPGC_OK, or IPGC_EBADCSR for the CSR ends or row pointers k_init found bad.
+int row_verdict(const Counters &c, int64_t m) {
+    if (c.bad_ends)
+        return fail(IPGC_EBADCSR, "rowptr[0]=%lld rowptr[n]=%lld, expected 0 and m=%lld", (long long)c.ends[0],
+                    (long long)c.ends[1], (long long)m);
+    if (c.bad_rows) return fail(IPGC_EBADCSR, "rowptr is decreasing or outside [0, m]");
+    return IPGC_OK;
+}
+
 int barrier_limit_ticks(int dev, int barrier_ms, uint64_t *ticks) {
     int khz = 0;
     HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
@@ -434,7 +443,7 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
     TRY(pf.end(kKindInit));
     HIP_TRY(hipGetLastError());
     TRY(read_counters(ws, s));
-    if (ws.host_ct->bad_rows) return fail(IPGC_EBADCSR, "rowptr is decreasing or outside [0, m]");
+    TRY(row_verdict(*ws.host_ct, m));
     const int64_t n_wide = (int64_t)ws.host_ct->class_n[kW] + ws.host_ct->class_n[kM];
     if (P.light == 0 || (P.light < 0 && n_wide > 0)) d.light_pull = kPushAll;
     else d.light_pull = n_wide > 0 ? kPullLight : kPullOnly;
@@ -484,9 +493,10 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
             TRY(pf.end(kKindPush));
             HIP_TRY(hipGetLastError());
             TRY(read_counters(ws, s));
-            if (ws.host_ct->finished) break;
+            if (ws.host_ct->finished || ws.host_ct->bad_ids) break;
         }
     }
+    if (ws.host_ct->bad_ids) return fail(IPGC_EBADCSR, "a column id is outside [0, n)");
     if (!ws.host_ct->finished) {
         unsigned aborted = 0;
         HIP_TRY(hipMemcpy(&aborted, &ws.bar.p->abort.v, sizeof aborted, hipMemcpyDeviceToHost));
@@ -551,14 +561,7 @@ int color_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, int64_t 
     Workspace &ws = workspace(dev);
     if (!ws.ct) TRY(ws.reserve(0, 0, 1, 1, kDefaultHubMin, false));
 
-    // rowptr[0] == 0 and rowptr[n] == m.
-    int32_t ends[2];
-    HIP_TRY(hipMemcpyAsync(&ends[0], rowptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&ends[1], rowptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (ends[0] != 0 || ends[1] != m)
-        return fail(IPGC_EBADCSR, "rowptr[0]=%d rowptr[n]=%d, expected 0 and m=%lld", ends[0], ends[1], (long long)m);
-
+    // rowptr[0] == 0 and rowptr[n] == m are checked by k_init, before any row is read
     int grid = 1, coop = 0;
     TRY(round_grid(ws, dev, P, n, &grid, &coop));
     DevT<int32_t> d{};
@@ -693,13 +696,6 @@ int color_noalloc_impl(const int32_t *rowptr, const int32_t *colidx, int64_t n, 
     prep_layout(n, &span, &prep_grid);
     size_t used = 0;
     TRY(ws.carve(base, kStaticScratchBytes, n, m, grid, prep_grid, P.hub_min, P.full, &used));
-
-    int32_t ends[2];
-    HIP_TRY(hipMemcpyAsync(&ends[0], rowptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&ends[1], rowptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (ends[0] != 0 || ends[1] != m)
-        return fail(IPGC_EBADCSR, "rowptr[0]=%d rowptr[n]=%d, expected 0 and m=%lld", ends[0], ends[1], (long long)m);
 
     DevT<int32_t> d{};
     d.rowptr = rowptr;

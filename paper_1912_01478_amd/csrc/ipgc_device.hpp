@@ -140,7 +140,16 @@ struct Counters {
     int32_t seg_overflow;             // a workgroup had more losers than its out segment holds (never expected)
     int32_t hub_chunks;               // row chunks of kRingChunk entries over all class-M nodes
     int32_t static_ident;             // class L or W holds every node: its static list is 0, 1, ..., n-1 (not written)
+    int32_t bad_ends;                 // rowptr[0] != 0 or rowptr[n] != m (their values in ends)
+    int64_t ends[2];
 };
+
+// True if the preparation kernels found the input unusable; the round kernels
+// then run no round (every workgroup reads the same flags) and the host
+// reports the error.
+__device__ __forceinline__ bool input_bad(const Counters *ct) {
+    return ct->bad_ends | ct->bad_rows | ct->bad_ids;
+}
 
 // A committed hub waiting for the push step.
 struct HubRec {
@@ -510,6 +519,12 @@ __global__ __launch_bounds__(kPrepBlock) void k_init(D d, int8_t *cls, int32_t s
     }
     if (__ballot(bad) && lane_id() == 0) d.ct->bad_rows = 1;
     if (__ballot(bad_id) && lane_id() == 0) d.ct->bad_ids = 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // the CSR ends: rowptr[0] == 0 and rowptr[n] == m
+        const int64_t r0 = d.rowptr[0], rn = d.rowptr[d.n];
+        d.ct->ends[0] = r0;
+        d.ct->ends[1] = rn;
+        if (r0 != 0 || rn != d.m) d.ct->bad_ends = 1;
+    }
     if (__ballot(unsorted) && lane_id() == 0) d.ct->unsorted = 1;
     __shared__ int s_cnt[kNumClasses + 1];
     __shared__ unsigned long long s_deg[kNumClasses];
@@ -1962,7 +1977,7 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
     GridBarrier gb;
     const bool up = gb.setup(d.bar, d.bar_limit);
     Units un;
-    if (!up) last = first - 1;  // a wait gave up: leave at once (the host reports it)
+    if (!up || input_bad(d.ct)) last = first - 1;  // a wait gave up, or unusable input: leave at once
     int32_t r = first;
     int G = gridDim.x;        // workgroups in the round loop
     int writers = gridDim.x;  // workgroups that wrote the list this round reads
@@ -2016,7 +2031,7 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
 // Stepped launches, discard mode: the rebuild of round r when round r - 1 kept no worklist.
 template <class D>
 __global__ __launch_bounds__(kRoundBlock) void k_rebuild_round(D d, int32_t r) {
-    if (d.ct->finished || r == 1 || !d.ct->prev_discarded) return;
+    if (d.ct->finished || r == 1 || !d.ct->prev_discarded || input_bad(d.ct)) return;
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
     load_segments(d, r & 1, pre, gridDim.x);
     const RoundIn in = round_view(d, r, pre);
@@ -2026,7 +2041,7 @@ __global__ __launch_bounds__(kRoundBlock) void k_rebuild_round(D d, int32_t r) {
 
 template <class D>
 __global__ __launch_bounds__(kRoundBlock) void k_assign_round(D d, int32_t r) {
-    if (d.ct->finished) return;
+    if (d.ct->finished || input_bad(d.ct)) return;
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
     if (r > 1) load_segments(d, r & 1, pre, gridDim.x);
     const RoundIn in = round_view(d, r, pre);
@@ -2039,7 +2054,7 @@ __global__ __launch_bounds__(kRoundBlock) void k_assign_round(D d, int32_t r) {
 
 template <class D>
 __global__ __launch_bounds__(kRoundBlock) void k_conflict_round(D d, int32_t r) {
-    if (d.ct->finished) return;
+    if (d.ct->finished || input_bad(d.ct)) return;
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
     if (r > 1) load_segments(d, r & 1, pre, gridDim.x);
     const RoundIn in = round_view(d, r, pre);
@@ -2051,7 +2066,7 @@ __global__ __launch_bounds__(kRoundBlock) void k_conflict_round(D d, int32_t r) 
 
 template <class D>
 __global__ __launch_bounds__(kRoundBlock) void k_push_round(D d) {
-    if (d.ct->finished) return;
+    if (d.ct->finished || input_bad(d.ct)) return;
     const int32_t nwon = d.ct->hub_winners;
     if (nwon == 0) return;
     Units un;
