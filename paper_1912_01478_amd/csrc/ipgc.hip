@@ -5,8 +5,9 @@
 // topology-driven or data-driven rounds chosen by worklist size against H).
 // The device code and its data layout are described in ipgc_device.hpp.
 //
-// One call: check the CSR ends, then (one stream, in order)
-//   k_init        initial state, node classes, row-pointer checks, class counts;
+// One call (one stream, in order):
+//   k_init        initial state, node classes, row-pointer checks (rowptr[0] == 0
+//                 and rowptr[n] == m among them), class counts;
 //                 column ids in range and sorted rows of the light nodes
 //                 (unless validation is off)
 //   k_offsets     prefix sums of the class counts, list layouts
