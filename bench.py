@@ -158,6 +158,7 @@ def parse():
     p.add_argument("--oracle-child", type=int, default=0, help=argparse.SUPPRESS)
     p.add_argument("--oracle-batch-worker", type=int, default=-1, help=argparse.SUPPRESS)
     p.add_argument("--oracle-procs", type=int, default=1, help=argparse.SUPPRESS)
+    p.add_argument("--oracle-cfg", type=int, default=4, help=argparse.SUPPRESS)
     p.add_argument("--pin", type=int, default=-1, help=argparse.SUPPRESS)
     return p.parse_args()
 
@@ -220,10 +221,11 @@ def finish_oracle_run(procs, cfg, timeout):
                       "pinned to core %d, generation excluded" % (NAMES[cfg], r["m"], r["rounds"], core)}
 
 
-def oracle_batch_worker(k: int, procs: int, count: int, seconds: float, core: int) -> None:
-    """Runs in a child process: graphs k, k + procs, k + 2 procs, ... of the batch workload, each
-    generated (untimed) and colored by the oracle (timed, single-threaded, pinned to one core),
-    until this worker's oracle time exceeds `seconds`; prints one JSON line."""
+def oracle_batch_worker(k: int, procs: int, count: int, seconds: float, core: int, cfg: int = 4) -> None:
+    """Runs in a child process: graphs k, k + procs, k + 2 procs, ... of the batch workload (cfg 4)
+    or of the serving stream's jobs (cfg 5), each generated (untimed) and colored by the oracle
+    (timed, single-threaded, pinned to one core), until this worker's oracle time exceeds
+    `seconds`; prints one JSON line."""
     if core >= 0:
         os.sched_setaffinity(0, {core})
     os.environ["OMP_NUM_THREADS"] = "1"
@@ -231,7 +233,7 @@ def oracle_batch_worker(k: int, procs: int, count: int, seconds: float, core: in
     import oracle
     graphs, entries, sec = [], 0, 0.0
     for g in range(k, count, procs):
-        gr = gg.batch_graph(4, g)
+        gr = gg.batch_graph(4, g) if cfg == 4 else gg.params_graph(gg.serving_job_params(5, g))
         t = time.perf_counter()
         oracle.color_graph(gr.rowptr, gr.colidx, trace_cap=1)
         sec += time.perf_counter() - t
@@ -242,7 +244,7 @@ def oracle_batch_worker(k: int, procs: int, count: int, seconds: float, core: in
     print(json.dumps({"worker": k, "graphs": graphs, "entries": entries, "seconds": sec}), flush=True)
 
 
-def batch_cpu_baseline(count, seconds, procs):
+def batch_cpu_baseline(count, seconds, procs, cfg=4):
     """The oracle over whole graphs of the batch: `procs` single-threaded worker processes, each
     pinned to its own core, each coloring graphs in index order (worker k takes k, k + procs, ...)
     for about `seconds` of oracle time.  The rate is the entries colored over the longest
@@ -253,7 +255,7 @@ def batch_cpu_baseline(count, seconds, procs):
         core = cores[k % len(cores)] if procs <= len(cores) else -1
         ps.append(subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-batch-worker", str(k),
                                     "--oracle-procs", str(procs), "--batch-graphs", str(count),
-                                    "--cpu-seconds", str(seconds), "--pin", str(core)],
+                                    "--cpu-seconds", str(seconds), "--pin", str(core), "--oracle-cfg", str(cfg)],
                                    stdout=subprocess.PIPE, stderr=subprocess.PIPE, cwd=ROOT))
     t0 = time.perf_counter()
     res = []
@@ -270,10 +272,12 @@ def batch_cpu_baseline(count, seconds, procs):
     return {"value": entries / longest, "unit": "edges/s", "cores": procs, "kind": "oracle", **host_info(),
             "cpu_seconds": round(sum(r["seconds"] for r in res), 2), "longest_worker_seconds": round(longest, 2),
             "wall_seconds_with_generation": round(wall, 2), "graphs": len(graphs), "entries": entries,
-            "sample": "%s: %d of %d graphs (%d entries; worker k takes graphs k, k+%d, ... in index order) colored "
+            "sample": "%s: %d of %d %s (%d entries; worker k takes %s k, k+%d, ... in index order) colored "
                       "by %d single-threaded oracle processes pinned one per core, about %.0f s of oracle time each; "
                       "rate = entries / the longest worker's oracle time" % (
-                          NAMES[4], len(graphs), count, entries, procs, procs, seconds)}
+                          NAMES[cfg] if count in (4096, 2000) else "%d-%s" % (count, "graph batch" if cfg == 4 else "job stream"),
+                          len(graphs), count, "graphs" if cfg == 4 else "jobs", entries,
+                          "graphs" if cfg == 4 else "jobs", procs, procs, seconds)}
 
 
 # ---------------------------------------------------------------- workloads on the device
@@ -621,6 +625,11 @@ def run_serving(args, pkg, gg, np):
             "peak_resident": st["peak_resident"], "rounds": st["rounds"], "steps": st["steps"]}
         log("load %.2f (%.1f jobs/s): p50 %.1f ms p99 %.1f ms" % (load, lam, runs["load_%.2f" % load]["p50_ms"],
                                                                   runs["load_%.2f" % load]["p99_ms"]))
+    cpu = None
+    if not args.no_cpu_baseline:
+        procs = args.cpu_procs or max(1, min(16, len(os.sched_getaffinity(0))))
+        cpu = batch_cpu_baseline(J, args.cpu_seconds, procs, cfg=5)
+        log("cpu oracle: %s -> %.3g edges/s" % (cpu["sample"], cpu["value"] or 0))
     key = "load_%.2f" % max(float(x) for x in args.loads.split(",")) if args.loads else "saturated"
     head = runs.get(key, runs["saturated"])
     nodes, edges = pkg.Server.capacity_for(int(args.budget_gb * (1 << 30)), avg_degree)
@@ -636,8 +645,7 @@ def run_serving(args, pkg, gg, np):
         "parity": parity, "runs": runs, "roofline": None,
         "roofline_note": "the server's round kernel is k_rounds over the resident union; its roofline is that of "
                          "configs 2 and 4, and this record is bound by host uploads and latency",
-        "cpu_baseline": None,
-        "cpu_baseline_note": "config 4's oracle sample covers the same job mix (90% of the jobs)",
+        "cpu_baseline": cpu,
     }
 
 
@@ -713,7 +721,7 @@ def main():
         return oracle_child(args.oracle_child, args.pin)
     if args.oracle_batch_worker >= 0:
         return oracle_batch_worker(args.oracle_batch_worker, args.oracle_procs, args.batch_graphs, args.cpu_seconds,
-                                   args.pin)
+                                   args.pin, args.oracle_cfg)
     if args.gpus != 1:
         print("bench.py: the library and this benchmark run on one GPU; --gpus %d is not supported (use --gpus 1)"
               % args.gpus, file=sys.stderr)
