@@ -262,3 +262,36 @@ def test_algorithmic_bytes_formula():
     r = run(g)
     assert r.wl_degree_sums.tolist() == [6, 5, 1]
     assert oracle.algorithmic_bytes(r) == 36 * (4 + 3 + 1) + 16 * (6 + 5 + 1)
+
+
+@pytest.mark.parametrize("n", [1, 5, 10, 37])
+def test_round_kinds_on_complete_graphs(n):
+    """Closed form of the schedule labels (Section IV, |WL| > H): on K_n the smallest active id is
+    the only node that commits each round, so |WL_r| = n - r + 1, and with H = floor(6n/10) exactly
+    the first n - H rounds are topology-driven (K_10: four of ten)."""
+    r = run(gg.complete(n))
+    assert r.wl_sizes.tolist() == list(range(n, 0, -1))
+    h = (6 * n) // 10
+    assert r.topology.tolist() == [1] * (n - h) + [0] * h
+    if n == 10:
+        assert r.topology.tolist() == [1, 1, 1, 1, 0, 0, 0, 0, 0, 0]
+
+
+@pytest.mark.parametrize("k", [1, 3, 9])
+def test_max_rounds_truncation_on_complete_graph(k):
+    """Stopping after k rounds on K_12 leaves exactly the first k nodes committed, with colors 1..k
+    (node i commits color i + 1 in round i + 1), and every other node uncolored (0)."""
+    g = gg.complete(12)
+    r = oracle.color_graph(g.rowptr, g.colidx, max_rounds=k)
+    assert r.colors.tolist() == list(range(1, k + 1)) + [0] * (12 - k)
+    assert r.rounds == k
+
+
+def test_max_rounds_truncation_on_path():
+    """P_6 in id order, traced by hand.  Round 1: every node holds tentative 1 and a node with a
+    smaller neighbour loses, so only node 0 commits (color 1).  Round 2: node 1 takes color 2 (its
+    committed neighbour 0 holds 1), nodes 2..5 take 1; node 1 wins, node 2 wins (its smaller
+    neighbour 1 holds tentative 2), nodes 3..5 lose.  After two rounds: [1, 2, 1, 0, 0, 0]."""
+    g = gg.path(6)
+    r = oracle.color_graph(g.rowptr, g.colidx, max_rounds=2)
+    assert r.colors.tolist() == [1, 2, 1, 0, 0, 0]
