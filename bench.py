@@ -422,7 +422,8 @@ def run_workload(args, torch, pkg, w, steps, warmup, cpu):
     table = at.TuneTable.load(args.tune_table or at.DEFAULT_TABLE)
     feats = w.features()
     if args.autotune:
-        choice, tms, dms, trials = at.tune(lambda s, **kw: w.call(stream=s, **kw), w.n, steps=args.tune_steps, log=log)
+        choice, tms, dms, trials = at.tune(lambda s, **kw: w.call(stream=s, **kw), w.n, steps=args.tune_steps, log=log,
+                                           knobs=at.BATCH_KNOBS if isinstance(w, Batch) else None)
         key = table.put(feats, choice, tms, dms, w.name, trials)
         table.save(args.tune_table or at.DEFAULT_TABLE)
         log("tuned %s: %s %.3f ms (defaults %.3f ms)" % (key, choice, tms, dms))
@@ -495,20 +496,34 @@ def run_workload(args, torch, pkg, w, steps, warmup, cpu):
         # each schedule with the other options as chosen (and, if tuned, the library defaults)
         for other in ("hybrid", "data", "topology", "rebuild"):
             okw = dict(kw, mode=other, threshold=0)
+            okw.pop("per_graph", None)  # one decision per round (the per-graph forms are timed below)
             w.call(**okw)
             oms, _ = median_ms(torch, w, okw, args.compare_steps)
             modes[other] = {"median_ms": round(oms, 3), "edges_per_s": w.m / (oms / 1000.0)}
             log("%s %s: %.3f ms" % (w.name, other, oms))
-        if kw["mode"] == "hybrid" and kw.get("threshold"):
+        if kw["mode"] == "hybrid" and kw.get("threshold") and not kw.get("per_graph"):
             modes["hybrid_tuned_H"] = {"median_ms": round(med, 3), "edges_per_s": w.m / (med / 1000.0),
                                        "threshold": kw["threshold"]}
+        if isinstance(w, Batch):
+            # the hybrid with a decision per graph (H_g = the same fraction of each graph's nodes):
+            # the paper's 60 %, and the tuned fraction
+            pg = [("hybrid_per_graph", 0)]
+            if kw["mode"] == "hybrid" and kw.get("threshold"):
+                pg.append(("hybrid_per_graph_tuned_H", kw["threshold"]))
+            for name, thr in pg:
+                pkw = dict(kw, mode="hybrid", threshold=thr, per_graph=True)
+                w.call(**pkw)
+                pms, _ = median_ms(torch, w, pkw, args.compare_steps)
+                modes[name] = {"median_ms": round(pms, 3), "edges_per_s": w.m / (pms / 1000.0), "threshold": thr}
+                log("%s %s: %.3f ms" % (w.name, name, pms))
         if choice is not None:
             dkw = at.call_kwargs(at.DEFAULT, w.n)
             w.call(**dkw)
             dms, _ = median_ms(torch, w, dkw, args.compare_steps)
             modes["defaults"] = {"median_ms": round(dms, 3), "edges_per_s": w.m / (dms / 1000.0)}
             log("%s library defaults: %.3f ms" % (w.name, dms))
-    best_h = min([modes[k]["median_ms"] for k in ("hybrid", "hybrid_tuned_H") if k in modes] or [med])
+    best_h = min([modes[k]["median_ms"] for k in ("hybrid", "hybrid_tuned_H", "hybrid_per_graph",
+                                                  "hybrid_per_graph_tuned_H") if k in modes] or [med])
     config = {"workload": w.name, "n": w.n, "m": w.m, "m_half": w.m // 2, "mode": kw["mode"], "rounds": rounds,
               "colors": num_colors, "valid": valid, "parallelism": "single-gpu",
               "options": {k: v for k, v in kw.items() if k != "mode"}, "tuning_class": at.class_key(feats),

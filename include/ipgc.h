@@ -147,12 +147,15 @@ enum {
                                   every assign instead of receiving them in a byte map (same result) */
     IPGC_FLAG_LIGHT_PUSH = 4,  /* every committed color is written into every neighbour's byte map.
                                   Neither flag: pull when no node is above light_max_degree, else push */
-    IPGC_FLAG_RACY = 8         /* in-place mode: a node that loses a conflict uncolors at once (a later
+    IPGC_FLAG_RACY = 8,        /* in-place mode: a node that loses a conflict uncolors at once (a later
                                   test in the same step no longer sees it) and light nodes also avoid
                                   their neighbours' visible tentative colors.  Fewer rounds, but the
                                   colors and round count depend on timing: the result is a proper
                                   coloring with colors in [1, deg+1], not the synchronous one.
                                   Implies IPGC_FLAG_LIGHT_PULL unless IPGC_FLAG_LIGHT_PUSH is given. */
+    IPGC_FLAG_PER_GRAPH = 16   /* ipgc_color_graphs_batched: every graph takes the schedule decision on its
+                                  own (see there).  The other entry points ignore it: for one graph the
+                                  decision is the same either way. */
 };
 
 /* Per-round record, filled on request.  Host memory owned by the caller. */
@@ -160,8 +163,11 @@ typedef struct ipgc_trace {
     int64_t capacity;    /* entries available in each array below */
     int32_t *wl_size;    /* |WL_r| at the start of round r (r = 0 .. rounds-1), may be NULL */
     int64_t *wl_degree;  /* sum of the degrees of the nodes in WL_r, may be NULL */
-    int8_t *topology;    /* 1 if round r ran topology-driven, 0 if data-driven, may be NULL */
+    int8_t *topology;    /* 1 if round r ran topology-driven, 0 if data-driven, may be NULL (per-graph
+                            batches: 1 if at least one graph ran it topology-driven) */
     int64_t recorded;    /* out: min(rounds, capacity) */
+    int32_t *topo_graphs; /* batches with IPGC_FLAG_PER_GRAPH: number of graphs that ran round r
+                            topology-driven, may be NULL (other calls leave it untouched) */
 } ipgc_trace;
 
 /*
@@ -227,6 +233,17 @@ int ipgc_color_graph_noalloc(const int32_t *csr_rowptr, const int32_t *csr_colid
  * and round count it gets alone.  One schedule decision is made per round for
  * the whole batch (topology-driven iff the batch's worklist exceeds H, by
  * default floor(6N/10) for N nodes in total).
+ *
+ * With IPGC_FLAG_PER_GRAPH each graph g decides for itself (Section IV applied to
+ * each graph): its round r is topology-driven iff its own worklist, its nodes not
+ * yet colored, holds more than H_g nodes, with H_g = floor(6 n_g / 10) by default
+ * and floor(H n_g / N) for a threshold H > 0 given in the options (each graph the
+ * same fraction of its nodes); TOPOLOGY and DATA give every graph that mode.  A
+ * round in which graphs of both kinds have work runs each step as a pass over
+ * the worklist for the data-driven graphs and a sweep over the nodes of the
+ * topology-driven ones.  The results are those of the default form.  Limits: at
+ * most 65536 graphs; not with IPGC_MODE_REBUILD (IPGC_EINVAL); the worklists take
+ * twice the device memory of the default form.
  *
  * num_graphs     number of graphs G >= 0.
  * node_off       HOST, G + 1 entries: graph g has nodes [node_off[g], node_off[g+1]) of the

@@ -49,6 +49,7 @@ FLAG_STEPPED = 1
 FLAG_LIGHT_PULL = 2
 FLAG_LIGHT_PUSH = 4
 FLAG_RACY = 8
+FLAG_PER_GRAPH = 16
 LIGHT = {"auto": 0, "pull": FLAG_LIGHT_PULL, "push": FLAG_LIGHT_PUSH}
 PROFILE_KINDS = 16
 
@@ -113,7 +114,8 @@ class Trace(ctypes.Structure):
     """Mirror of ``ipgc_trace``."""
     _fields_ = [("capacity", ctypes.c_int64), ("wl_size", ctypes.POINTER(ctypes.c_int32)),
                 ("wl_degree", ctypes.POINTER(ctypes.c_int64)),
-                ("topology", ctypes.POINTER(ctypes.c_int8)), ("recorded", ctypes.c_int64)]
+                ("topology", ctypes.POINTER(ctypes.c_int8)), ("recorded", ctypes.c_int64),
+                ("topo_graphs", ctypes.POINTER(ctypes.c_int32))]
 
 
 _lib = None
@@ -280,7 +282,7 @@ class _Call:
 
     def __init__(self, threshold, light_max_degree, hub_min_degree, validate, stepped, trace, trace_cap,
                  profile_mask, timeline, workgroups=0, light="auto", racy=False, tail_workgroups=0,
-                 barrier_timeout_ms=0):
+                 barrier_timeout_ms=0, per_graph=False):
         self.prof = None
         if profile_mask or timeline:
             self.prof = Profile(int(profile_mask))
@@ -289,7 +291,8 @@ class _Call:
                 self.prof.phase_ticks = ctypes.cast(self._ticks, ctypes.POINTER(ctypes.c_uint64))
                 self.prof.phase_capacity = int(timeline)
         self.opts = Options(int(threshold), int(light_max_degree), int(hub_min_degree), int(validate),
-                            (FLAG_STEPPED if stepped else 0) | LIGHT[light] | (FLAG_RACY if racy else 0),
+                            (FLAG_STEPPED if stepped else 0) | LIGHT[light] | (FLAG_RACY if racy else 0) |
+                            (FLAG_PER_GRAPH if per_graph else 0),
                             ctypes.pointer(self.prof) if self.prof is not None else None, int(workgroups),
                             int(tail_workgroups), int(barrier_timeout_ms), 0)
         self.tr = None
@@ -298,9 +301,11 @@ class _Call:
             self._wl = (ctypes.c_int32 * cap)()
             self._wd = (ctypes.c_int64 * cap)()
             self._topo = (ctypes.c_int8 * cap)()
+            self._tg = (ctypes.c_int32 * cap)() if per_graph else None
             self.tr = Trace(cap, ctypes.cast(self._wl, ctypes.POINTER(ctypes.c_int32)),
                             ctypes.cast(self._wd, ctypes.POINTER(ctypes.c_int64)),
-                            ctypes.cast(self._topo, ctypes.POINTER(ctypes.c_int8)), 0)
+                            ctypes.cast(self._topo, ctypes.POINTER(ctypes.c_int8)), 0,
+                            ctypes.cast(self._tg, ctypes.POINTER(ctypes.c_int32)) if per_graph else None)
 
     def trace_ref(self):
         return ctypes.byref(self.tr) if self.tr is not None else None
@@ -311,6 +316,8 @@ class _Call:
             res.wl_sizes = list(self._wl[:k])
             res.wl_degrees = list(self._wd[:k])
             res.topology = list(self._topo[:k])
+            if self._tg is not None:
+                res.topo_graphs = list(self._tg[:k])
         if self.prof is not None:
             res.profile = self.prof.as_dict()
         return res
@@ -436,6 +443,7 @@ class BatchColoring:
     wl_degrees: list | None = None  # per round of the batch: degree sum over that union
     topology: list | None = None
     profile: dict | None = None
+    topo_graphs: list | None = None  # per-graph schedules: graphs run topology-driven per round
 
     def graph(self, g: int):
         return self.colors[int(self.node_off[g]):int(self.node_off[g + 1])]
@@ -446,12 +454,14 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
                          stepped: bool = False, out=None, stream=None, trace: bool = False,
                          profile_mask: int = 0, workgroups: int = 0, light: str = "auto",
                          racy: bool = False, tail_workgroups: int = 0, barrier_timeout_ms: int = 0,
-                         timeline: int = 0) -> BatchColoring:
+                         timeline: int = 0, per_graph: bool = False) -> BatchColoring:
     """Color many graphs in one launch.  ``rowptr_packed`` (int32[N+G]) and ``colidx_packed``
     (int32[M]) are device tensors in the layout of ``pack_graphs``; ``node_off`` and ``edge_off``
     (G+1 int64 each) are host arrays.  Each graph gets the coloring and round count it gets alone.
     ``trace``, ``profile_mask`` and ``timeline`` are as for ``color_graph``, over the rounds of the
-    whole batch."""
+    whole batch.  ``per_graph`` lets every graph take its own schedule decision (H_g, the
+    ``threshold`` scaled to its node count; ``IPGC_FLAG_PER_GRAPH``); with ``trace`` the result
+    then also holds the number of graphs that ran each round topology-driven."""
     import numpy as np
     import torch
 
@@ -475,7 +485,7 @@ def color_graphs_batched(rowptr_packed, colidx_packed, node_off, edge_off, mode=
     elif out.dtype != torch.int32 or out.numel() != N or not out.is_contiguous() or out.device != dev:
         raise ValueError("out must be a contiguous int32 tensor of N entries on the batch's device")
     call = _Call(threshold, light_max_degree, hub_min_degree, validate, stepped, trace, N, profile_mask, timeline,
-                 workgroups, light, racy, tail_workgroups, barrier_timeout_ms)
+                 workgroups, light, racy, tail_workgroups, barrier_timeout_ms, per_graph)
     rounds = np.full(max(G, 1), -1, dtype=np.int32)
     if stream is None:
         stream = torch.cuda.current_stream(dev)

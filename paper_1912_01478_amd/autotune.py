@@ -33,6 +33,9 @@ KNOBS = {
     "light": ["auto", "pull", "push"],
     "tail_workgroups": [0, -1, 32, 64, 128],
 }
+# Batches also try every graph deciding on its own (IPGC_FLAG_PER_GRAPH), H_g the same fraction of
+# each graph's nodes as H is of the batch's.
+BATCH_KNOBS = dict(KNOBS, schedule=KNOBS["schedule"] + ["per_graph", "per_graph_h20", "per_graph_h10"])
 DEFAULT = {"workgroups": 0, "light_max_degree": 0, "hub_min_degree": 0, "schedule": "hybrid", "light": "auto",
            "tail_workgroups": 0}
 TABLE_VERSION = 1
@@ -41,12 +44,19 @@ DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_
 
 def schedule_args(schedule: str, n: int) -> dict:
     """Mode and threshold of a schedule name: "hybrid" (H = floor(6n/10)), "hybrid_hK" (H = floor(K n/100),
-    i.e. topology-driven rounds only while more than K% of the nodes are active), "data", "topology"."""
+    i.e. topology-driven rounds only while more than K% of the nodes are active), "data", "topology".
+    Batches only: "per_graph" and "per_graph_hK" are the same with a decision per graph (H_g =
+    floor(6 n_g/10), or about K% of each graph's nodes)."""
     if schedule in ("hybrid", "data", "topology", "rebuild"):
         return {"mode": schedule, "threshold": 0}
     if schedule.startswith("hybrid_h"):
         pct = int(schedule[len("hybrid_h"):])
         return {"mode": "hybrid", "threshold": max(1, (pct * n) // 100)}
+    if schedule == "per_graph":
+        return {"mode": "hybrid", "threshold": 0, "per_graph": True}
+    if schedule.startswith("per_graph_h"):
+        pct = int(schedule[len("per_graph_h"):])
+        return {"mode": "hybrid", "threshold": max(1, (pct * n) // 100), "per_graph": True}
     raise ValueError("unknown schedule %r" % schedule)
 
 

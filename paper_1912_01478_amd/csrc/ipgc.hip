@@ -104,6 +104,8 @@ struct Workspace {
     DBuf<uint32_t> pend;
     DBuf<int64_t> growptr, node_off, edge_off;  // batches: union row starts, graph offsets
     DBuf<int32_t> gbase, gidx, grounds;         // batches: per-node graph base and index, rounds per graph
+    DBuf<int32_t> gthr, gleft, trace_topo;      // per-graph schedules: H_g, uncolored nodes per graph, trace
+    DBuf<uint32_t> gsplit;                      // per-graph schedules, stepped launches: each graph's kind
     DBuf<uint64_t> ticks;
     DBuf<Barrier> bar;
     DBuf<Counters> ctb;
@@ -117,10 +119,11 @@ struct Workspace {
 
     // Every buffer one call of the single-graph or batched path needs, with its entry count, in
     // one fixed order (the batched path adds its union arrays itself).  At most m / (hub_min + 1)
-    // nodes have a degree above hub_min, so no more hubs can commit in one round.
+    // nodes have a degree above hub_min, so no more hubs can commit in one round.  Per-graph
+    // schedules (split) double the worklist segments: a round may append the losers of two passes.
     template <class Fn>
-    int plan(int64_t n, int64_t m, int grid, int prep_grid, int hub_min, bool full, Fn &&f) {
-        const int64_t seg = n + (int64_t)kNumClasses * grid * (kRoundBlock + 1);
+    int plan(int64_t n, int64_t m, int grid, int prep_grid, int hub_min, bool full, bool split, Fn &&f) {
+        const int64_t seg = (n + (int64_t)kNumClasses * grid * (kRoundBlock + 1)) * (split ? 2 : 1);
         TRY(f(ctb, 1));
         TRY(f(bar, 1));
         TRY(f(static_list, n));
@@ -149,8 +152,8 @@ struct Workspace {
         return IPGC_OK;
     }
 
-    int reserve(int64_t n, int64_t m, int grid, int prep_grid, int hub_min, bool full) {
-        TRY(plan(n, m, grid, prep_grid, hub_min, full, [](auto &b, int64_t c) { return b.reserve(c); }));
+    int reserve(int64_t n, int64_t m, int grid, int prep_grid, int hub_min, bool full, bool split = false) {
+        TRY(plan(n, m, grid, prep_grid, hub_min, full, split, [](auto &b, int64_t c) { return b.reserve(c); }));
         ct = ctb.p;
         if (!host_ct) HIP_TRY(hipHostMalloc(&host_ct, sizeof(Counters), hipHostMallocDefault));
         return IPGC_OK;
@@ -162,7 +165,7 @@ struct Workspace {
     int carve(unsigned char *base, size_t size, int64_t n, int64_t m, int grid, int prep_grid, int hub_min, bool full,
               size_t *used) {
         size_t off = 0;
-        TRY(plan(n, m, grid, prep_grid, hub_min, full, [&](auto &b, int64_t c) {
+        TRY(plan(n, m, grid, prep_grid, hub_min, full, false, [&](auto &b, int64_t c) {
             using T = std::remove_reference_t<decltype(*b.p)>;
             off = (off + 255) & ~(size_t)255;
             const size_t bytes = sizeof(T) * (size_t)c;
@@ -188,6 +191,7 @@ struct Workspace {
         seg_deg.release(); block_deg.release(); units.release(); trace_deg.release(); cls.release();
         F.release(); mask.release(); pend.release(); ticks.release(); bar.release(); growptr.release(); node_off.release(); edge_off.release();
         gbase.release(); gidx.release(); grounds.release(); ctb.release(); sorted_rows.release();
+        gthr.release(); gleft.release(); trace_topo.release(); gsplit.release();
         if (host_ct && !borrowed) (void)hipHostFree(host_ct);
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
         *this = Workspace();
@@ -249,13 +253,15 @@ int cooperative_capacity(Workspace &ws, int dev, int *out) {
         int coop = 0, cus = 0, per_cu = 0;
         HIP_TRY(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        // the two instantiations (one graph, batches) must both fit
-        int per_cu64 = 0;
+        // the three instantiations (one graph, batches, batches with per-graph schedules) must all fit
+        int per_cu64 = 0, per_cu_split = 0;
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &per_cu, reinterpret_cast<const void *>(k_rounds<DevT<int32_t>>), kRoundBlock, 0));
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
             &per_cu64, reinterpret_cast<const void *>(k_rounds<DevT<int64_t>>), kRoundBlock, 0));
-        per_cu = std::min(per_cu, per_cu64);
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu_split, reinterpret_cast<const void *>(k_rounds<DevT<int64_t, true>>), kRoundBlock, 0));
+        per_cu = std::min(per_cu, std::min(per_cu64, per_cu_split));
         ws.coop_blocks = coop ? std::min(kMaxRoundBlocks, std::max(0, cus * per_cu)) : 0;
     }
     *out = ws.coop_blocks;
@@ -282,12 +288,14 @@ int parse_options(const ipgc_options *opt, int mode, Params *p) {
     if (o.barrier_timeout_ms < -1) return fail(IPGC_EINVAL, "barrier_timeout_ms %d below -1", o.barrier_timeout_ms);
     p->barrier_ms = o.barrier_timeout_ms == 0 ? 60000 : o.barrier_timeout_ms;
     p->full = o.validate == IPGC_VALIDATE_FULL;
-    if (o.flags & ~(IPGC_FLAG_STEPPED | IPGC_FLAG_LIGHT_PULL | IPGC_FLAG_LIGHT_PUSH | IPGC_FLAG_RACY))
+    if (o.flags & ~(IPGC_FLAG_STEPPED | IPGC_FLAG_LIGHT_PULL | IPGC_FLAG_LIGHT_PUSH | IPGC_FLAG_RACY |
+                    IPGC_FLAG_PER_GRAPH))
         return fail(IPGC_EINVAL, "unknown flags 0x%x", o.flags);
     if ((o.flags & IPGC_FLAG_LIGHT_PULL) && (o.flags & IPGC_FLAG_LIGHT_PUSH))
         return fail(IPGC_EINVAL, "IPGC_FLAG_LIGHT_PULL and IPGC_FLAG_LIGHT_PUSH exclude each other");
     p->light = (o.flags & IPGC_FLAG_LIGHT_PULL) ? 1 : (o.flags & IPGC_FLAG_LIGHT_PUSH) ? 0 : -1;
     p->racy = (o.flags & IPGC_FLAG_RACY) != 0;
+    p->per_graph = (o.flags & IPGC_FLAG_PER_GRAPH) != 0;
     if (p->racy && p->light < 0) p->light = 1;
     if (o.workgroups < 0) return fail(IPGC_EINVAL, "negative workgroups %d", o.workgroups);
     p->workgroups = o.workgroups;
@@ -362,8 +370,8 @@ void prep_layout(int64_t n, int64_t *span, int *prep_grid) {
 // IPGC_VALIDATE_FULL on a graph whose row pointers and ids have passed their
 // checks: sorted copies of the rows in the workspace, then self-loops,
 // repeated ids and missing reverse entries.
-template <typename Off>
-int check_full(Workspace &ws, hipStream_t s, const DevT<Off> &d, int64_t n, int64_t m) {
+template <class D>
+int check_full(Workspace &ws, hipStream_t s, const D &d, int64_t n, int64_t m) {
     TRY(ws.sorted_rows.reserve(std::max<int64_t>(m, 1)));  // in the plan when full validation is on
     TRY(clear(&ws.ct->bad_full, sizeof(int32_t), s));
     const int sort_grid = (int)std::min<int64_t>(n, 65536);
@@ -377,13 +385,13 @@ int check_full(Workspace &ws, hipStream_t s, const DevT<Off> &d, int64_t n, int6
 
 // Everything after the input is in place: d.rowptr, d.colidx, d.c and (for a
 // batch) d.gbase / d.gidx / d.node_off / d.grounds are set by the caller.
-template <typename Off>
-int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int64_t n, int64_t m, int grid,
+template <class D>
+int run(Workspace &ws, int dev, hipStream_t s, const Params &P, D d, int64_t n, int64_t m, int grid,
         int coop, int32_t *out_rounds, ipgc_trace *trace) {
     int64_t span = 0;
     int prep_grid = 0;
     prep_layout(n, &span, &prep_grid);
-    TRY(ws.reserve(n, m, grid, prep_grid, P.hub_min, P.full));
+    TRY(ws.reserve(n, m, grid, prep_grid, P.hub_min, P.full, d.gthr != nullptr));
     ipgc_profile *prof = P.prof;
     Profiler pf{ws, s, prof ? prof->mask : 0u, {}, 0};
 
@@ -476,7 +484,7 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
         int32_t first = 1, last = (int32_t)std::min<int64_t>(n + 1, INT32_MAX - 2);
         void *args[] = {&d, &first, &last};
         TRY(pf.begin(kKindRounds));
-        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rounds<DevT<Off>>), dim3(grid),
+        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rounds<D>), dim3(grid),
                                            dim3(kRoundBlock), args, 0, s));
         TRY(pf.end(kKindRounds));
         TRY(read_counters(ws, s));
@@ -515,8 +523,17 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, DevT<Off> d, int
         if (k > 0 && trace->wl_degree)
             HIP_TRY(hipMemcpyAsync(trace->wl_degree, ws.trace_deg.p, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (k > 0 && trace->topology && trace->wl_size)
+        if (d.trace_topo) {  // per-graph schedules: the device counted the graphs of each kind
+            const int64_t kt = std::min<int64_t>(k, d.topo_cap);
+            std::vector<int32_t> tg((size_t)std::max<int64_t>(kt, 1));
+            if (kt > 0) HIP_TRY(hipMemcpy(tg.data(), d.trace_topo, sizeof(int32_t) * kt, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < kt; ++i) {
+                if (trace->topo_graphs) trace->topo_graphs[i] = tg[i];
+                if (trace->topology) trace->topology[i] = (int8_t)(tg[i] > 0);
+            }
+        } else if (k > 0 && trace->topology && trace->wl_size) {
             for (int64_t i = 0; i < k; ++i) trace->topology[i] = (int8_t)((int64_t)trace->wl_size[i] > H);
+        }
         trace->recorded = k;
     }
     if (prof) {
@@ -592,6 +609,11 @@ int batch_impl(int64_t graphs, const int64_t *node_off, const int64_t *edge_off,
     if (n >= INT32_MAX) return fail(IPGC_ETOOBIG, "the batch has %lld nodes, more than int32 ids allow", (long long)n);
     Params P;
     TRY(parse_options(opt, mode, &P));
+    if (P.per_graph && P.mode == IPGC_MODE_REBUILD)
+        return fail(IPGC_EINVAL, "IPGC_FLAG_PER_GRAPH does not combine with IPGC_MODE_REBUILD");
+    if (P.per_graph && graphs > kMaxSplitGraphs)
+        return fail(IPGC_EINVAL, "IPGC_FLAG_PER_GRAPH takes at most %d graphs (%lld given)", kMaxSplitGraphs,
+                    (long long)graphs);
     if (n == 0) {
         for (int64_t g = 0; g < graphs; ++g) out_rounds[g] = 0;
         g_err[0] = 0;
@@ -620,16 +642,52 @@ int batch_impl(int64_t graphs, const int64_t *node_off, const int64_t *edge_off,
 
     int grid = 1, coop = 0;
     TRY(round_grid(ws, dev, P, n, &grid, &coop));
-    DevT<int64_t> d{};
-    d.rowptr = ws.growptr.p;
-    d.colidx = colidx_packed;
-    d.gbase = ws.gbase.p;
-    d.gidx = ws.gidx.p;
-    d.gend = ws.node_off.p + 1;
-    d.grounds = ws.grounds.p;
-    d.c = out_colors_packed;
+    auto setup = [&](auto &d) {
+        d.rowptr = ws.growptr.p;
+        d.colidx = colidx_packed;
+        d.gbase = ws.gbase.p;
+        d.gidx = ws.gidx.p;
+        d.gend = ws.node_off.p + 1;
+        d.grounds = ws.grounds.p;
+        d.c = out_colors_packed;
+    };
     int32_t rounds = -1;
-    TRY(run(ws, dev, s, P, d, n, m, grid, coop, &rounds, trace));
+    std::vector<int32_t> h_thr, h_left;  // per-graph schedules (alive until the call has synchronized)
+    if (P.per_graph) {
+        // H_g per graph, and every graph's worklist (its uncolored nodes) at the start of round 1
+        h_thr.resize((size_t)graphs);
+        h_left.resize((size_t)graphs);
+        const int64_t Hc = std::min<int64_t>(P.threshold, n);  // H >= N: no graph is ever above it
+        for (int64_t g = 0; g < graphs; ++g) {
+            const int64_t ng = node_off[g + 1] - node_off[g];
+            h_left[g] = (int32_t)ng;
+            if (P.mode == IPGC_MODE_TOPOLOGY) h_thr[g] = -1;
+            else if (P.mode == IPGC_MODE_DATA) h_thr[g] = INT32_MAX;
+            else h_thr[g] = (int32_t)(P.threshold > 0 ? Hc * ng / n : (6 * ng) / 10);
+        }
+        TRY(ws.gthr.reserve(graphs));
+        TRY(ws.gleft.reserve(graphs));
+        TRY(ws.gsplit.reserve((graphs + 63) / 64 * 2));
+        HIP_TRY(hipMemcpyAsync(ws.gthr.p, h_thr.data(), sizeof(int32_t) * graphs, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(ws.gleft.p, h_left.data(), sizeof(int32_t) * graphs, hipMemcpyHostToDevice, s));
+        DevT<int64_t, true> d{};
+        setup(d);
+        d.gthr = ws.gthr.p;
+        d.gleft = ws.gleft.p;
+        d.gsplit = ws.gsplit.p;
+        d.ngraphs = (int32_t)graphs;
+        const int64_t tcap = trace ? std::min<int64_t>(n, std::max<int64_t>(trace->capacity, 0)) : 0;
+        if (tcap > 0) {
+            TRY(ws.trace_topo.reserve(tcap));
+            d.trace_topo = ws.trace_topo.p;
+            d.topo_cap = tcap;
+        }
+        TRY(run(ws, dev, s, P, d, n, m, grid, coop, &rounds, trace));
+    } else {
+        DevT<int64_t> d{};
+        setup(d);
+        TRY(run(ws, dev, s, P, d, n, m, grid, coop, &rounds, trace));
+    }
     HIP_TRY(hipMemcpyAsync(out_rounds, ws.grounds.p, sizeof(int32_t) * graphs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     g_err[0] = 0;
@@ -746,7 +804,7 @@ const char *ipgc_kernel_name(int kind) { return kind >= 0 && kind < ipgc::kNumKi
 
 const char *ipgc_unit_name(int kind) { return kind >= 0 && kind < ipgc::kNumUnits ? ipgc::kUnitNames[kind] : ""; }
 
-int ipgc_version(void) { return (2 << 16) | 0; }
+int ipgc_version(void) { return (2 << 16) | 1; }
 
 void ipgc_release_workspaces(void) {
     std::lock_guard<std::mutex> lock(ipgc::g_mutex);

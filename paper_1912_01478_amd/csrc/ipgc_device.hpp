@@ -80,6 +80,7 @@ constexpr int kMaxXcc = 16;
 constexpr int kWideScanMax = 65536;      // rounds with at most this many active nodes scan rings 4 chunks a pass
 constexpr int kMaskColors = 64;          // colors 1..64 of committed neighbours are bits of a word per node
 constexpr int kRingChunk = 2048;         // row entries of a class-M node whose ring part one wavefront builds
+constexpr int kMaxSplitGraphs = 65536;   // per-graph schedules: graphs of a batch at most (a bit each in shared memory)
 
 enum { kL = 0, kW = 1, kM = 2, kNumClasses = 3 };
 
@@ -141,6 +142,8 @@ struct Counters {
     int32_t hub_chunks;               // row chunks of kRingChunk entries over all class-M nodes
     int32_t static_ident;             // class L or W holds every node: its static list is 0, 1, ..., n-1 (not written)
     int32_t bad_ends;                 // rowptr[0] != 0 or rowptr[n] != m (their values in ends)
+    int32_t split_topo;               // per-graph schedules, stepped launches: graphs with active nodes of
+    int32_t split_data;               // each kind in the current round (written by its assign launch)
     int64_t ends[2];
 };
 
@@ -162,9 +165,10 @@ struct HubRec {
 // Everything a kernel needs, passed by value.  Off is the type of the row
 // offsets: int32_t for one graph, int64_t for a packed batch of graphs, which
 // the kernels see as one graph (the disjoint union) with global node ids.
-template <typename Off>
+template <typename Off, bool SPLIT = false>
 struct DevT {
     using OffT = Off;
+    static constexpr bool kSplit = SPLIT;  // per-graph schedules compiled in (batches only)
     const Off *rowptr;       // row starts, n + 1 entries (a batch: union row starts)
     const int32_t *colidx;   // column indices (a batch: ids local to each graph)
     const int32_t *gbase;    // a batch: first global id of each node's graph (null for one graph)
@@ -212,6 +216,12 @@ struct DevT {
     int32_t discard;         // topology-driven rounds keep no worklist; it is rebuilt when data rounds start
     int32_t tail_groups;     // workgroups that stay in the round loop for small data-driven rounds (0: all)
     uint64_t bar_limit;      // wall-clock ticks a grid-barrier wait may last
+    const int32_t *gthr;     // a batch with per-graph schedules: H_g per graph (null: one decision per round)
+    uint32_t *gsplit;        // per-graph schedules, stepped launches: bit g set iff graph g runs
+                             // topology-driven in the current round (the assign launch writes it)
+    int32_t *trace_topo;     // per-graph schedules: graphs run topology-driven per round (null: not kept)
+    int64_t topo_cap;        // entries of trace_topo
+    int32_t ngraphs;         // per-graph schedules: graphs in the batch
 
     // global id of a neighbour stored in row entry k of node v
     __device__ __forceinline__ int32_t base(int32_t v) const { return gbase ? gbase[v] : 0; }
@@ -597,7 +607,8 @@ __global__ __launch_bounds__(1024) void k_offsets(D d, int32_t prep_grid) {
         for (int k = 0; k < kNumClasses; ++k) {
             d.ct->static_off[k] = off[k];
             d.ct->class_n[k] = off[k + 1] - off[k];
-            const int32_t cap = (d.ct->class_n[k] + d.grid - 1) / d.grid + kRoundBlock;
+            // a round of both kinds (per-graph schedules) appends the losers of two passes
+            const int32_t cap = ((d.ct->class_n[k] + d.grid - 1) / d.grid + kRoundBlock) * (d.gthr ? 2 : 1);
             d.ct->seg_cap[k] = cap;
             d.ct->seg_off[k] = so;
             so += (int64_t)cap * d.grid;
@@ -999,7 +1010,77 @@ struct RoundIn {
     int32_t wl[kNumClasses];  // worklist entries per class (the active nodes)
     int32_t total;            // worklist size |WL_r|
     bool topo;
+    bool split;               // per-graph schedules, a round of both kinds: this view takes only the nodes
+                              // of graphs whose kind of round is `topo` (graph_bits)
 };
+
+// ============================================================== per-graph schedules (batches)
+//
+// With per-graph thresholds every graph of a batch takes the decision of Section IV on its own:
+// its round r is topology-driven iff its worklist (its nodes not yet committed, gleft) holds more
+// than H_g nodes.  A round in which graphs of both kinds still have active nodes runs each step
+// twice: over the worklist for the nodes of data-driven graphs and as a sweep of the static list
+// for the nodes of topology-driven ones.  One graph's nodes are all handled by one of the two
+// passes, so every graph sees exactly the round it would see alone.
+
+// The instantiation for batches with per-graph schedules; the others carry none of their code.
+template <class D>
+constexpr bool kSplitDev = D::kSplit;
+
+// Bit g set iff graph g runs topology-driven in this round (shared memory, one copy per workgroup).
+__device__ __forceinline__ uint32_t *graph_bits() {
+    __shared__ uint32_t s_bits[kMaxSplitGraphs / 32];
+    return s_bits;
+}
+
+struct Split {
+    int32_t topo;  // graphs with active nodes that run this round topology-driven
+    int32_t data;  // graphs with active nodes that run it data-driven
+};
+
+// The kind of round of every graph into graph_bits, and how many graphs have each kind.  All
+// threads of the workgroup call this while gleft does not change (before any commit of the
+// round).  initial: from the node counts, as at the start of round 1.
+template <class D>
+__device__ __forceinline__ Split graph_split(const D &d, bool initial) {
+    __shared__ int s_n[2];
+    uint32_t *bits = graph_bits();
+    if (threadIdx.x < 2) s_n[threadIdx.x] = 0;
+    __syncthreads();
+    const int lane = lane_id();
+    for (int g0 = (int)(threadIdx.x / kWave) * kWave; g0 < d.ngraphs; g0 += (int)blockDim.x) {
+        const int g = g0 + lane;
+        int64_t left = 0;
+        if (g < d.ngraphs)
+            left = initial ? d.gend[g] - (g > 0 ? d.gend[g - 1] : 0) : (int32_t)ld_agent((unsigned *)&d.gleft[g]);
+        const bool topo = g < d.ngraphs && left > 0 && left > (int64_t)d.gthr[g];  // a done graph has no round
+        const uint64_t tm = __ballot(topo), dm = __ballot(left > 0 && !topo);
+        if (lane == 0) {  // kMaxSplitGraphs / 32 words hold 64 graphs per wavefront step
+            bits[g0 >> 5] = (uint32_t)tm;
+            bits[(g0 >> 5) + 1] = (uint32_t)(tm >> 32);
+            if (tm) atomicAdd(&s_n[0], (int)__popcll(tm));
+            if (dm) atomicAdd(&s_n[1], (int)__popcll(dm));
+        }
+    }
+    __syncthreads();
+    const Split sp{s_n[0], s_n[1]};
+    __syncthreads();  // s_n is reset by the next call
+    return sp;
+}
+
+// True if item v of a view is not this view's work: a committed node met by a sweep, or, in a
+// round of both kinds, a node of a graph handled by the other pass.
+template <class D>
+__device__ __forceinline__ bool skip_item(const D &d, const RoundIn &in, int32_t v, int32_t cv) {
+    bool skip = in.topo && cv > 0;
+    if constexpr (kSplitDev<D>) {
+        if (in.split) {
+            const int32_t g = d.gidx[v];
+            skip = skip || (bool)(graph_bits()[g >> 5] >> (g & 31) & 1u) != in.topo;
+        }
+    }
+    return skip;
+}
 
 // Load the segment counts of list `src` and build the prefix sums in shared
 // memory (all threads of the workgroup call this).
@@ -1019,8 +1100,10 @@ __device__ __forceinline__ void load_segments(const D &d, int src, int32_t (*pre
     __syncthreads();
 }
 
+// The items of round r: the static list (round 1, topology-driven rounds) or the segmented list.
+// force: -1 decides by |WL| > H, 0 and 1 set data- or topology-driven (per-graph schedules).
 template <class D>
-__device__ __forceinline__ RoundIn round_view(const D &d, int r, int32_t (*pre)[kMaxRoundBlocks + 1]) {
+__device__ __forceinline__ RoundIn round_view(const D &d, int r, int32_t (*pre)[kMaxRoundBlocks + 1], int force = -1) {
     RoundIn in;
     int32_t tot[kNumClasses];
     if (r == 1) {
@@ -1030,7 +1113,8 @@ __device__ __forceinline__ RoundIn round_view(const D &d, int r, int32_t (*pre)[
     }
     in.total = tot[0] + tot[1] + tot[2];
     for (int k = 0; k < kNumClasses; ++k) in.wl[k] = tot[k];
-    in.topo = (int64_t)in.total > d.threshold;
+    in.topo = force < 0 ? (int64_t)in.total > d.threshold : force > 0;
+    in.split = false;
     const int src = r & 1;  // round r reads list (r & 1) written by round r-1
     for (int k = 0; k < kNumClasses; ++k) {
         if (r == 1 || in.topo) {
@@ -1129,15 +1213,96 @@ __device__ __forceinline__ void map_assign_wave(const D &d, int32_t v, Units &un
 // kLightK * kLightC loads outstanding where a node alone has a chain of dependent ones.  A
 // wavefront takes items b0 + j * 64 + lane (j < kLightK) of a block of 64 * kLightK consecutive
 // items, so every load of a step is coalesced across the wavefront when the items are.
+// Per-graph schedules, a round of both kinds: the light items of graphs handled by the other
+// pass become absent (no node, not active).
 constexpr int kLightK = 2;  // nodes per lane
 constexpr int kLightC = 4;  // row entries per node per pass
+
+// Per-graph schedules, a round of both kinds: the light items of graphs handled by the other
+// pass become absent (no node, not active).
+template <bool TOPO, class D>
+__device__ __forceinline__ void drop_other_part(const D &d, int32_t (&v)[kLightK], uint32_t &act) {
+#pragma unroll
+    for (int j = 0; j < kLightK; ++j) {
+        if (v[j] < 0) continue;
+        const int32_t g = d.gidx[v[j]];
+        if ((bool)(graph_bits()[g >> 5] >> (g & 31) & 1u) != TOPO) {
+            v[j] = -1;
+            act &= ~(1u << j);
+        }
+    }
+}
 
 // Tentative colors of the class-L items (Section II-C, first fit): the first zero bit of the
 // node's color mask (push modes: committed neighbours set bit t - 1; d <= 32 neighbours leave a
 // zero among the first 33 bits), or of a mask of the committed colors read from the
 // neighbours' states (pull modes).  TOPO: a sweep over the static list, committed nodes skipped.
+// The blocks of a light sweep in a round of both kinds (per-graph schedules): first, first + step,
+// ... below total, leaving out blocks that hold only nodes of one data-driven graph.  Each lane
+// judges one of the wavefront's next 64 blocks from the graphs of its first and last node (a block
+// whose ends lie in different graphs is kept), so 64 blocks cost one round trip.
+struct LightBlocks {
+    int64_t base, step;
+    int32_t total;
+    uint64_t keep = 0;  // bit j: block base + j * step still to run
+    bool fresh = true;
+    __device__ LightBlocks(int64_t first, int64_t step_, int32_t total_) : base(first), step(step_), total(total_) {}
+    template <class D>
+    __device__ __forceinline__ bool next(const D &d, const ClassView &cv, int64_t *b0) {
+        while (!keep) {  // the same for the whole wavefront
+            if (!fresh) base += kWave * step;
+            fresh = false;
+            if (base >= total) return false;
+            const int64_t bj = base + (int64_t)lane_id() * step;
+            bool k = false;
+            if (bj < total) {
+                const int32_t v1 = cv.at_in((int32_t)bj, 0, 1);
+                const int32_t v2 = cv.at_in((int32_t)min<int64_t>(bj + kWave * kLightK, total) - 1, 0, 1);
+                const int32_t g1 = d.gidx[v1], g2 = d.gidx[v2];
+                k = g1 != g2 || (graph_bits()[g1 >> 5] >> (g1 & 31) & 1u);
+            }
+            keep = __ballot(k);
+        }
+        const int j = __ffsll((unsigned long long)keep) - 1;
+        keep &= keep - 1;
+        *b0 = base + (int64_t)j * step;
+        return true;
+    }
+};
+
+// The blocks of a light pass: b0 = first, first + step, ... below total.  With per-graph schedules
+// compiled in, the sweep of a round of both kinds (filt) leaves out the blocks of data-driven
+// graphs; the other instantiations iterate plainly.
+template <bool SPLIT>
+struct LightIter {
+    int64_t step;
+    int32_t total;
+    __device__ LightIter(int64_t, int64_t step_, int32_t total_, bool) : step(step_), total(total_) {}
+    template <class D>
+    __device__ __forceinline__ bool more(const D &, const ClassView &, int64_t &b0) const { return b0 < total; }
+    __device__ __forceinline__ void advance(int64_t &b0) const { b0 += step; }
+};
+
+template <>
+struct LightIter<true> {
+    LightBlocks lb;
+    int64_t step;
+    int32_t total;
+    bool filt;
+    __device__ LightIter(int64_t first, int64_t step_, int32_t total_, bool filt_)
+        : lb(first, step_, total_), step(step_), total(total_), filt(filt_) {}
+    template <class D>
+    __device__ __forceinline__ bool more(const D &d, const ClassView &cv, int64_t &b0) {
+        return filt ? lb.next(d, cv, &b0) : b0 < total;
+    }
+    __device__ __forceinline__ void advance(int64_t &b0) const {
+        if (!filt) b0 += step;
+    }
+};
+
+
 template <bool TOPO, class D>
-__device__ __forceinline__ void light_assign(const D &d, const ClassView &cv, Units &un, int G) {
+__device__ __forceinline__ void light_assign(const D &d, const ClassView &cv, bool split, Units &un, int G) {
     using Off = typename D::OffT;
     constexpr int K = kLightK, C = kLightC;
     const int lane = lane_id();
@@ -1146,30 +1311,34 @@ __device__ __forceinline__ void light_assign(const D &d, const ClassView &cv, Un
     const int64_t gw = (int64_t)(threadIdx.x / kWave) * G + blockIdx.x;
     const int64_t nw = (int64_t)G * (blockDim.x / kWave);
     const int32_t total = cv.total;
-    for (int64_t b0 = gw * (kWave * K); b0 < total; b0 += nw * (kWave * K)) {
+    LightIter<kSplitDev<D>> it(gw * (kWave * K), nw * (kWave * K), total, TOPO && split);
+    for (int64_t b0 = gw * (kWave * K); it.more(d, cv, b0); it.advance(b0)) {
         int slo, shi;
         cv.range((int32_t)b0, (int32_t)min<int64_t>(b0 + kWave * K, total) - 1, &slo, &shi);
         int32_t v[K];
         uint32_t act = 0;  // bit j: item j of this lane is an active node
-#pragma unroll
+    #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int64_t i = b0 + j * kWave + lane;
             v[j] = i < total ? cv.at_in((int32_t)i, slo, shi) : -1;
             act |= (i < total ? 1u : 0u) << j;
         }
+        if constexpr (kSplitDev<D>) {
+            if (split) drop_other_part<TOPO>(d, v, act);
+        }
         if (TOPO) {
             int32_t c0[K];
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j) c0[j] = v[j] >= 0 ? d.c[v[j]] : 1;
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j)
                 if (c0[j] > 0) act &= ~(1u << j);
         }
         if (d.light_pull == kPushAll) {
             uint64_t mk[K];
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j) mk[j] = act >> j & 1u ? d.mask[v[j]] : 0ull;
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j)
                 if (act >> j & 1u) d.c[v[j]] = -__ffsll((unsigned long long)~mk[j]);
             un.u[kUMapBytes] += 8 * __popc(act);
@@ -1179,7 +1348,7 @@ __device__ __forceinline__ void light_assign(const D &d, const ClassView &cv, Un
         Off b[K];
         int32_t len[K], gb[K];
         uint64_t used[K];
-#pragma unroll
+    #pragma unroll
         for (int j = 0; j < K; ++j) {
             const bool a = act >> j & 1u;
             b[j] = a ? d.rowptr[v[j]] : 0;
@@ -1189,18 +1358,18 @@ __device__ __forceinline__ void light_assign(const D &d, const ClassView &cv, Un
         }
         for (int32_t q0 = 0;; q0 += C) {
             int32_t cu[K][C];
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j)
-#pragma unroll
+    #pragma unroll
                 for (int q = 0; q < C; ++q) cu[j][q] = q0 + q < len[j] ? d.colidx[b[j] + q0 + q] + gb[j] : -1;
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j)
-#pragma unroll
+    #pragma unroll
                 for (int q = 0; q < C; ++q) cu[j][q] = cu[j][q] >= 0 ? d.c[cu[j][q]] : 0;
             bool more = false;
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j) {
-#pragma unroll
+    #pragma unroll
                 for (int q = 0; q < C; ++q) {
                     const int32_t x = d.racy ? iabs(cu[j][q]) : cu[j][q];  // racy: in-flight tentatives too
                     if (x > 0 && x <= 64) used[j] |= 1ull << (x - 1);
@@ -1209,7 +1378,7 @@ __device__ __forceinline__ void light_assign(const D &d, const ClassView &cv, Un
             }
             if (!more) break;
         }
-#pragma unroll
+    #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (!(act >> j & 1u)) continue;
             d.c[v[j]] = -__ffsll((unsigned long long)~used[j]);
@@ -1219,15 +1388,9 @@ __device__ __forceinline__ void light_assign(const D &d, const ClassView &cv, Un
     }
 }
 
-// Conflict test, commit and push of the class-L items (Section II-C): v loses iff a smaller
-// neighbour holds its tentative color t.  Pull-only graphs scan the row up to v (sorted rows
-// stop there); push modes scan only the positions still pending, and drop from them the
-// neighbours found committed (their colors have reached v's mask).  Losers go to the
-// workgroup's class-L segment with one shared-memory atomic per wavefront (ballot and popcount
-// give each its slot); winners commit and, in push modes, set bit t - 1 (t <= 33) in their
-// neighbours' masks.
+
 template <bool TOPO, class D>
-__device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, int64_t seg_base, bool discard,
+__device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, bool split, int64_t seg_base, bool discard,
                                                int32_t r, Units &un, int G, int32_t *list, int32_t seg_cap,
                                                int *s_cnt, unsigned long long *s_deg) {
     using Off = typename D::OffT;
@@ -1239,28 +1402,32 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
     const int64_t nw = (int64_t)G * (blockDim.x / kWave);
     const int32_t total = cv.total;
     const bool pull_only = d.light_pull == kPullOnly;
-    for (int64_t b0 = gw * (kWave * K); b0 < total; b0 += nw * (kWave * K)) {
+    LightIter<kSplitDev<D>> it(gw * (kWave * K), nw * (kWave * K), total, TOPO && split);
+    for (int64_t b0 = gw * (kWave * K); it.more(d, cv, b0); it.advance(b0)) {
         int slo, shi;
         cv.range((int32_t)b0, (int32_t)min<int64_t>(b0 + kWave * K, total) - 1, &slo, &shi);
         int32_t v[K], t[K];
         uint32_t act = 0;  // bit j: item j is an active node
-#pragma unroll
+    #pragma unroll
         for (int j = 0; j < K; ++j) {
             const int64_t i = b0 + j * kWave + lane;
             v[j] = i < total ? cv.at_in((int32_t)i, slo, shi) : -1;
             act |= (i < total ? 1u : 0u) << j;
         }
-#pragma unroll
+        if constexpr (kSplitDev<D>) {
+            if (split) drop_other_part<TOPO>(d, v, act);
+        }
+    #pragma unroll
         for (int j = 0; j < K; ++j) t[j] = v[j] >= 0 ? -d.c[v[j]] : 0;
         if (TOPO) {
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j)
                 if (t[j] < 0) act &= ~(1u << j);  // committed (c > 0)
         }
         Off b[K];
         int32_t len[K], gb[K];
         uint32_t pm[K];  // pull-only: unused; push modes: pending positions not yet scanned
-#pragma unroll
+    #pragma unroll
         for (int j = 0; j < K; ++j) {
             const bool a = act >> j & 1u;
             b[j] = a ? d.rowptr[v[j]] : 0;
@@ -1271,13 +1438,13 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
         uint32_t lose = 0, done = ~act;  // bit j
         uint32_t seen[K];                // push modes: positions found committed
         int32_t read = 0;
-#pragma unroll
+    #pragma unroll
         for (int j = 0; j < K; ++j) seen[j] = 0;
         for (int32_t q0 = 0;; q0 += C) {
             int32_t pos[K][C], u[K][C];
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j)
-#pragma unroll
+    #pragma unroll
                 for (int q = 0; q < C; ++q) {
                     if (pull_only) {
                         pos[j][q] = !(done >> j & 1u) && q0 + q < len[j] ? q0 + q : -1;
@@ -1286,18 +1453,18 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
                         pm[j] &= pm[j] - 1;
                     }
                 }
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j)
-#pragma unroll
+    #pragma unroll
                 for (int q = 0; q < C; ++q) u[j][q] = pos[j][q] >= 0 ? d.colidx[b[j] + pos[j][q]] + gb[j] : INT32_MAX;
             int32_t cu[K][C];
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j)
-#pragma unroll
+    #pragma unroll
                 for (int q = 0; q < C; ++q) cu[j][q] = u[j][q] < v[j] ? d.c[u[j][q]] : 0;
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j) {
-#pragma unroll
+    #pragma unroll
                 for (int q = 0; q < C; ++q) {
                     if (done >> j & 1u) continue;
                     if (u[j][q] >= v[j]) {  // not a smaller neighbour; past the row's end if INT32_MAX
@@ -1316,7 +1483,7 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
             if ((done & ((1u << K) - 1)) == (1u << K) - 1) break;
         }
         if (!pull_only) {
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j)
                 if (seen[j]) atomicAnd(&d.pend[v[j]], ~seen[j]);
         }
@@ -1326,7 +1493,7 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
         int nl = 0;
         int64_t ldeg = 0;
         uint64_t lm[K];
-#pragma unroll
+    #pragma unroll
         for (int j = 0; j < K; ++j) {
             lm[j] = __ballot(lose >> j & 1u);
             nl += __popcll(lm[j]);
@@ -1344,7 +1511,7 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
                 if (lane == 0) d.ct->seg_overflow = 1;
                 lose = 0;
             }
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j) {
                 if (lose >> j & 1u) {
                     if (d.racy) d.c[v[j]] = 0;
@@ -1354,7 +1521,7 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
             }
         }
         // winners commit
-#pragma unroll
+    #pragma unroll
         for (int j = 0; j < K; ++j) {
             if (!(win >> j & 1u)) continue;
             d.c[v[j]] = t[j];
@@ -1368,21 +1535,21 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
         if (!pull_only && win) {
             for (int32_t q0 = 0;; q0 += C) {
                 int32_t w[K][C];
-#pragma unroll
+    #pragma unroll
                 for (int j = 0; j < K; ++j)
-#pragma unroll
+    #pragma unroll
                     for (int q = 0; q < C; ++q)
                         w[j][q] = (win >> j & 1u) && q0 + q < len[j] ? d.colidx[b[j] + q0 + q] + gb[j] : -1;
                 uint64_t mw[K][C];
-#pragma unroll
+    #pragma unroll
                 for (int j = 0; j < K; ++j)
-#pragma unroll
+    #pragma unroll
                     for (int q = 0; q < C; ++q) mw[j][q] = w[j][q] >= 0 ? d.mask[w[j][q]] : ~0ull;
                 bool more = false;
-#pragma unroll
+    #pragma unroll
                 for (int j = 0; j < K; ++j) {
                     const uint64_t bit = 1ull << ((t[j] - 1) & 63);
-#pragma unroll
+    #pragma unroll
                     for (int q = 0; q < C; ++q)
                         if (!(mw[j][q] & bit)) atomicOr((unsigned long long *)&d.mask[w[j][q]], (unsigned long long)bit);
                     more |= (win >> j & 1u) && q0 + C < len[j];
@@ -1393,7 +1560,7 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
         if (d.grounds) {
             // per item j: lanes committing nodes of the same graph as the first committing lane
             // share one atomic
-#pragma unroll
+    #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const bool wj = win >> j & 1u;
                 const int32_t g = wj ? d.gidx[v[j]] : -1;
@@ -1421,8 +1588,8 @@ __device__ __forceinline__ void assign_step(const D &d, const RoundIn &in, Units
     const int64_t gw = gt / kWave, nw = nt / kWave;
     const int lane = lane_id();
     // class L: a lane per node, several nodes in flight per lane
-    if (in.topo) light_assign<true>(d, in.cv[kL], un, G);
-    else light_assign<false>(d, in.cv[kL], un, G);
+    if (in.topo) light_assign<true>(d, in.cv[kL], in.split, un, G);
+    else light_assign<false>(d, in.cv[kL], in.split, un, G);
     // classes W and M.  Large rounds (at least four W/M nodes per wavefront): a thread per node
     // for the first zero bit of the color mask; nodes whose mask is full (64 colors taken) are
     // queued in shared memory and each gets a wavefront for its byte map from color 65 on (the
@@ -1440,7 +1607,7 @@ __device__ __forceinline__ void assign_step(const D &d, const RoundIn &in, Units
             if (i < nWM) {
                 v = i < nW ? in.cv[kW].at((int32_t)i) : in.cv[kM].at((int32_t)(i - nW));
                 const int32_t cv = d.c[v];
-                if (!(in.topo && cv > 0)) {
+                if (!skip_item(d, in, v, cv)) {
                     const uint64_t free = ~d.mask[v];
                     un.u[kUMapBytes] += 8;
                     if (free) {
@@ -1463,7 +1630,7 @@ __device__ __forceinline__ void assign_step(const D &d, const RoundIn &in, Units
         for (int64_t i = gw; i < nWM; i += nw) {
             const int32_t v = i < nW ? in.cv[kW].at((int32_t)i) : in.cv[kM].at((int32_t)(i - nW));
             const int32_t cv = d.c[v];
-            if (in.topo && cv > 0) continue;
+            if (skip_item(d, in, v, cv)) continue;
             const uint64_t free = ~d.mask[v];
             un.u[kUMapBytes] += lane == 0 ? 8 : 0;
             if (free) {
@@ -1639,7 +1806,7 @@ __device__ __forceinline__ void conflict_wide_teams(const D &d, const RoundIn &i
         if (act) {
             v = hub ? in.cv[kM].at((int32_t)(i - nW)) : in.cv[kW].at((int32_t)i);
             const int32_t cv = d.c[v];
-            act = !(in.topo && cv > 0);
+            act = !skip_item(d, in, v, cv);
             t = -cv;
             b = d.rowptr[v];
             e = d.rowptr[v + 1];
@@ -1726,14 +1893,53 @@ __device__ __forceinline__ void conflict_wide_teams(const D &d, const RoundIn &i
     }
 }
 
+// Conflict test, commit and push of W/M node v (item of class W, or M if hub) by a group of S
+// lanes (this lane is gl of them).
 template <class D>
-__device__ __forceinline__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, int32_t r, Units &un, int G) {
+__device__ __forceinline__ void wide_conflict_item(const D &d, const RoundIn &in, const OutSegs &os, int32_t r, Units &un,
+                                                   int32_t v, int32_t cv, bool hub, int S, int gl, bool discard,
+                                                   const int64_t (&seg_base)[kNumClasses], int *s_cnt,
+                                                   unsigned long long *s_deg) {
+    const int32_t t = -cv;
+    const bool lose = ring_scan_group(d, v, t, in.total <= kWideScanMax ? 4 : 1, S, un);
+    const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
+    const int q = hub ? kM : kW;
+    if (gl == 0) un.u[kUConflictNodes] += 1;
+    if (lose) {
+        if (gl == 0) {
+            if (d.racy) d.c[v] = 0;
+            const int p = atomicAdd(&s_cnt[q], 1);
+            atomicAdd(&s_deg[q], (unsigned long long)(e - b));
+            if (!discard) os.list[seg_base[q] + p] = v;
+        }
+    } else {
+        if (gl == 0) {
+            d.c[v] = t;
+            un.u[kUCommits] += 1;
+            if (d.grounds) atomicMax(&d.grounds[d.gidx[v]], r);
+            if (d.gleft) atomicSub(&d.gleft[d.gidx[v]], 1);
+        }
+        if (hub) {
+            if (gl == 0) d.hub_won[atomicAdd(&d.ct->hub_winners, 1)] = HubRec{b, e, d.fshift(v), t, d.base(v)};
+        } else {
+            push_row(d, b, e, t, d.base(v), d.fshift(v), gl, S);
+            un.u[kUPushEntries] += gl == 0 ? e - b : 0;
+        }
+    }
+}
+
+// part: 0 the round's only pass; 1 and 2 the two passes of a round of both kinds (per-graph
+// schedules), whose losers share the workgroup's out segments: the first clears the counts, the
+// second writes them.
+template <class D>
+__device__ __forceinline__ void conflict_step(const D &d, const RoundIn &in, const OutSegs &os, int32_t r, Units &un, int G,
+                                              int part = 0) {
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)G * blockDim.x;
     const int64_t gw = gt / kWave, nw = nt / kWave;
     const int lane = lane_id();
     __shared__ int s_cnt[kNumClasses];
     __shared__ unsigned long long s_deg[kNumClasses];
-    if (threadIdx.x < kNumClasses) {
+    if (part != 2 && threadIdx.x < kNumClasses) {
         s_cnt[threadIdx.x] = 0;
         s_deg[threadIdx.x] = 0;
     }
@@ -1757,6 +1963,35 @@ __device__ __forceinline__ void conflict_step(const D &d, const RoundIn &in, con
         const int S = ph == 0 && !quarter ? kWave : cnt >= 8 * nw ? 8 : cnt >= 4 * nw ? 16 : kWave;
         const int64_t lo = ph == 0 ? 0 : (quarter ? nW : nWM), hi = ph == 0 && quarter ? nW : nWM;
         const int per = kWave / S, gl = lane % S;
+        if constexpr (kSplitDev<D>) {
+            if (in.split && in.topo) {
+                // the sweep of a round of both kinds: each lane judges one of the wavefront's next 64
+                // items (iteration lane / per, slot lane % per), and the groups take only the kept ones
+                const int64_t step = nw * per;
+                for (int64_t w0 = lo + gw * per; w0 < hi; w0 += (int64_t)(kWave / per) * step) {
+                    const int64_t ij = w0 + (int64_t)(lane / per) * step + lane % per;
+                    int32_t vj = 0, cj = 0;
+                    bool need = false;
+                    if (ij < hi) {
+                        vj = ij >= nW ? in.cv[kM].at((int32_t)(ij - nW)) : in.cv[kW].at((int32_t)ij);
+                        cj = d.c[vj];
+                        need = !skip_item(d, in, vj, cj);
+                    }
+                    const int hj = ij >= nW ? 1 : 0;
+                    uint64_t nm = __ballot(need);
+                    while (nm) {  // the same for the whole wavefront
+                        uint64_t mm = nm;
+                        for (int q = lane / S; q > 0 && mm; --q) mm &= mm - 1;
+                        const int src = mm ? __ffsll((unsigned long long)mm) - 1 : 0;
+                        const int32_t v = __shfl(vj, src), cv = __shfl(cj, src);
+                        const bool hub = __shfl(hj, src) != 0;
+                        for (int q = 0; q < per && nm; ++q) nm &= nm - 1;
+                        if (mm) wide_conflict_item(d, in, os, r, un, v, cv, hub, S, gl, discard, seg_base, s_cnt, s_deg);
+                    }
+                }
+                continue;
+            }
+        }
         // the loop is the same for the whole wavefront; group lane / S takes item i0 + lane / S
         for (int64_t i0 = lo + gw * per; i0 < hi; i0 += nw * per) {
             const int64_t i = i0 + lane / S;
@@ -1764,40 +1999,15 @@ __device__ __forceinline__ void conflict_step(const D &d, const RoundIn &in, con
             const bool hub = i >= nW;
             const int32_t v = hub ? in.cv[kM].at((int32_t)(i - nW)) : in.cv[kW].at((int32_t)i);
             const int32_t cv = d.c[v];
-            if (in.topo && cv > 0) continue;
-            const int32_t t = -cv;
-            const bool lose = ring_scan_group(d, v, t, in.total <= kWideScanMax ? 4 : 1, S, un);
-            const int64_t b = d.rowptr[v], e = d.rowptr[v + 1];
-            const int q = hub ? kM : kW;
-            if (gl == 0) un.u[kUConflictNodes] += 1;
-            if (lose) {
-                if (gl == 0) {
-                    if (d.racy) d.c[v] = 0;
-                    const int p = atomicAdd(&s_cnt[q], 1);
-                    atomicAdd(&s_deg[q], (unsigned long long)(e - b));
-                    if (!discard) os.list[seg_base[q] + p] = v;
-                }
-            } else {
-                if (gl == 0) {
-                    d.c[v] = t;
-                    un.u[kUCommits] += 1;
-                    if (d.grounds) atomicMax(&d.grounds[d.gidx[v]], r);
-                    if (d.gleft) atomicSub(&d.gleft[d.gidx[v]], 1);
-                }
-                if (hub) {
-                    if (gl == 0) d.hub_won[atomicAdd(&d.ct->hub_winners, 1)] = HubRec{b, e, d.fshift(v), t, d.base(v)};
-                } else {
-                    push_row(d, b, e, t, d.base(v), d.fshift(v), gl, S);
-                    un.u[kUPushEntries] += gl == 0 ? e - b : 0;
-                }
-            }
+            if (skip_item(d, in, v, cv)) continue;
+            wide_conflict_item(d, in, os, r, un, v, cv, hub, S, gl, discard, seg_base, s_cnt, s_deg);
         }
     }
     // class L: a lane per node, several nodes in flight per lane
-    if (in.topo) light_conflict<true>(d, in.cv[kL], seg_base[kL], discard, r, un, G, os.list, os.cap[kL], s_cnt, s_deg);
-    else light_conflict<false>(d, in.cv[kL], seg_base[kL], discard, r, un, G, os.list, os.cap[kL], s_cnt, s_deg);
+    if (in.topo) light_conflict<true>(d, in.cv[kL], in.split, seg_base[kL], discard, r, un, G, os.list, os.cap[kL], s_cnt, s_deg);
+    else light_conflict<false>(d, in.cv[kL], in.split, seg_base[kL], discard, r, un, G, os.list, os.cap[kL], s_cnt, s_deg);
     __syncthreads();
-    if (threadIdx.x < kNumClasses) {
+    if (part != 1 && threadIdx.x < kNumClasses) {
         os.cnt[threadIdx.x * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
         os.deg[threadIdx.x * gridDim.x + blockIdx.x] = (int64_t)s_deg[threadIdx.x];
     }
@@ -1964,6 +2174,25 @@ __device__ __forceinline__ int round_groups(const D &d, const RoundIn &in, int G
     return (int64_t)in.total <= (int64_t)d.tail_groups * kTailNodesPerGroup ? d.tail_groups : G;
 }
 
+// Per-graph schedules, round r > 1: the view of the first pass (the worklist, or the static list
+// when no graph runs data-driven), and whether a sweeping second pass follows.
+template <class D>
+__device__ __forceinline__ RoundIn graph_round(const D &d, int r, int32_t (*pre)[kMaxRoundBlocks + 1], Split sp,
+                                               bool *two) {
+    *two = sp.topo > 0 && sp.data > 0;
+    RoundIn in = round_view(d, r, pre, sp.topo > 0 && sp.data == 0 ? 1 : 0);
+    in.split = *two;
+    return in;
+}
+
+// The second pass of a round of both kinds: the static list, nodes of topology-driven graphs.
+template <class D>
+__device__ __forceinline__ RoundIn sweep_view(const D &d, int r, int32_t (*pre)[kMaxRoundBlocks + 1]) {
+    RoundIn in = round_view(d, r, pre, 1);
+    in.split = true;
+    return in;
+}
+
 // Rounds first .. last (or until the worklist is empty) in one cooperative
 // launch: assign | barrier | conflict | barrier [| hub push | barrier].  Every
 // workgroup reads the same counts after each barrier, so all take the same
@@ -1982,9 +2211,25 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
     int G = gridDim.x;        // workgroups in the round loop
     int writers = gridDim.x;  // workgroups that wrote the list this round reads
     bool discarded = false;   // the previous round kept no worklist
+    bool split_live = true;   // per-graph schedules: some graph may still run topology-driven
     for (; r <= last; ++r) {
         if (r > 1) load_segments(d, r & 1, pre, writers);
         RoundIn in = round_view(d, r, pre);
+        bool two = false;  // per-graph schedules: a round of both kinds (a second, sweeping pass)
+        if constexpr (kSplitDev<D>) {
+            if (d.gthr) {
+                // every workgroup reads gleft before the assign barrier, so before any commit of round r
+                Split sp{0, 0};
+                if (r == 1) {
+                    if (blockIdx.x == 0) sp = graph_split(d, true);
+                } else if (split_live) {
+                    sp = graph_split(d, false);
+                    split_live = sp.topo > 0;  // gleft only shrinks: a data-driven graph stays data-driven
+                }
+                if (r > 1) in = graph_round(d, r, pre, sp, &two);
+                if (blockIdx.x == 0 && threadIdx.x == 0 && r - 1 < d.topo_cap) d.trace_topo[r - 1] = sp.topo;
+            }
+        }
         if (discarded && !in.topo && in.total > 0) {
             rebuild_step(d, r & 1, G);
             if (!gb.sync()) break;
@@ -1995,7 +2240,8 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
         discarded = d.discard && in.topo;
         if (blockIdx.x == 0) round_record(d, r, in, false, writers);
         if (in.total == 0) break;
-        const int g2 = round_groups(d, in, G);
+        // a round of both kinds keeps every workgroup: its sweep spreads the whole static list
+        const int g2 = two ? G : round_groups(d, in, G);
         if (g2 < G) {
             if ((int)blockIdx.x >= g2) break;
             gb.shrink(g2);
@@ -2004,10 +2250,12 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
         tick(d, 3 * (int64_t)(r - 1));
         if (r > 1) {  // round 1's tentative colors (all 1) were set at init
             assign_step(d, in, un, G);
+            if (two) assign_step(d, sweep_view(d, r, pre), un, G);
             if (!gb.sync()) break;
         }
         tick(d, 3 * (int64_t)(r - 1) + 1);
-        conflict_step(d, in, out_segs(d, r), r, un, G);
+        conflict_step(d, in, out_segs(d, r), r, un, G, two ? 1 : 0);
+        if (two) conflict_step(d, sweep_view(d, r, pre), out_segs(d, r), r, un, G, 2);
         writers = G;
         if (!gb.sync()) break;
         tick(d, 3 * (int64_t)(r - 1) + 2);
@@ -2044,11 +2292,28 @@ __global__ __launch_bounds__(kRoundBlock) void k_assign_round(D d, int32_t r) {
     if (d.ct->finished || input_bad(d.ct)) return;
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
     if (r > 1) load_segments(d, r & 1, pre, gridDim.x);
-    const RoundIn in = round_view(d, r, pre);
+    RoundIn in = round_view(d, r, pre);
+    bool two = false;
+    if constexpr (kSplitDev<D>) {
+        if (d.gthr) {  // per-graph schedules: decided here, from gleft before any commit of round r
+            Split sp{0, 0};
+            if (r > 1 || blockIdx.x == 0) sp = graph_split(d, r == 1);
+            if (r > 1) in = graph_round(d, r, pre, sp, &two);
+            if (blockIdx.x == 0) {  // for this round's conflict launch
+                if (threadIdx.x == 0) {
+                    d.ct->split_topo = sp.topo;
+                    d.ct->split_data = sp.data;
+                    if (r - 1 < d.topo_cap) d.trace_topo[r - 1] = sp.topo;
+                }
+                for (int w = threadIdx.x; w < (d.ngraphs + 63) / 64 * 2; w += blockDim.x) d.gsplit[w] = graph_bits()[w];
+            }
+        }
+    }
     if (blockIdx.x == 0) round_record(d, r, in, true, gridDim.x);
     if (in.total == 0 || r == 1) return;  // round 1's tentative colors were set at init
     Units un;
     assign_step(d, in, un, gridDim.x);
+    if (two) assign_step(d, sweep_view(d, r, pre), un, gridDim.x);
     un.flush(d);
 }
 
@@ -2057,10 +2322,22 @@ __global__ __launch_bounds__(kRoundBlock) void k_conflict_round(D d, int32_t r) 
     if (d.ct->finished || input_bad(d.ct)) return;
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];
     if (r > 1) load_segments(d, r & 1, pre, gridDim.x);
-    const RoundIn in = round_view(d, r, pre);
+    RoundIn in = round_view(d, r, pre);
+    bool two = false;
+    if constexpr (kSplitDev<D>) {
+        if (d.gthr && r > 1) {  // the decision of this round's assign launch
+            const Split sp{d.ct->split_topo, d.ct->split_data};
+            in = graph_round(d, r, pre, sp, &two);
+            if (two) {
+                for (int w = threadIdx.x; w < (d.ngraphs + 63) / 64 * 2; w += blockDim.x) graph_bits()[w] = d.gsplit[w];
+                __syncthreads();
+            }
+        }
+    }
     if (in.total == 0) return;
     Units un;
-    conflict_step(d, in, out_segs(d, r), r, un, gridDim.x);
+    conflict_step(d, in, out_segs(d, r), r, un, gridDim.x, two ? 1 : 0);
+    if (two) conflict_step(d, sweep_view(d, r, pre), out_segs(d, r), r, un, gridDim.x, 2);
     un.flush(d);
 }
 

@@ -123,6 +123,7 @@ struct Params {
     int tail_groups = 0;    // workgroups kept for small data-driven rounds (0: all)
     int light = -1;         // -1: automatic, 0: push into every byte map, 1: class L pulls
     bool racy = false;      // in-place (timing-dependent) mode
+    bool per_graph = false; // batches: a schedule decision per graph (H_g) instead of one per round
     int mode = IPGC_MODE_HYBRID;
     ipgc_profile *prof = nullptr;
 };

@@ -47,7 +47,7 @@ def test_version(lib):
 MIRRORS = {
     "ipgc_options": ("Options", ["threshold", "light_max_degree", "hub_min_degree", "validate", "flags", "profile",
                                  "workgroups", "tail_workgroups", "barrier_timeout_ms", "reserved"]),
-    "ipgc_trace": ("Trace", ["capacity", "wl_size", "wl_degree", "topology", "recorded"]),
+    "ipgc_trace": ("Trace", ["capacity", "wl_size", "wl_degree", "topology", "recorded", "topo_graphs"]),
     "ipgc_profile": ("Profile", ["mask", "kinds", "ms", "launches", "unit_kinds", "reserved", "units", "phase_ticks",
                                  "phase_capacity", "phase_recorded", "tick_khz"]),
     "ipgc_server_config": ("ServerConfig", ["node_capacity", "edge_capacity", "max_jobs", "rounds_per_step", "mode",
@@ -90,6 +90,18 @@ def test_struct_layouts_match_header(c_layouts, cname):
     assert [f for f, _ in cls._fields_] == fields
     for f in fields:
         assert getattr(cls, f).offset == c_layouts[(cname, f)], (cname, f)
+
+
+def test_flags_match_header():
+    """Every IPGC_FLAG_* value of the header is the binding's FLAG_* value of the same name."""
+    import re
+
+    import paper_1912_01478_amd as pkg
+    with open(os.path.join(ROOT, "include", "ipgc.h")) as f:
+        flags = dict(re.findall(r"IPGC_FLAG_(\w+) = (\d+)", f.read()))
+    assert set(flags) == {"STEPPED", "LIGHT_PULL", "LIGHT_PUSH", "RACY", "PER_GRAPH"}
+    for name, value in flags.items():
+        assert getattr(pkg, "FLAG_" + name) == int(value), name
 
 
 def test_kernel_names(lib):

@@ -36,6 +36,11 @@ def test_call_kwargs():
     assert at.call_kwargs({"schedule": "topology"}, 50)["mode"] == "topology"
     with pytest.raises(ValueError):
         at.schedule_args("sometimes", 10)
+    assert at.call_kwargs({"schedule": "per_graph_h10"}, 1000)["per_graph"] is True
+    assert at.call_kwargs({"schedule": "per_graph"}, 1000)["threshold"] == 0
+    assert "per_graph" not in at.call_kwargs({"schedule": "hybrid"}, 1000)
+    assert set(at.KNOBS["schedule"]) < set(at.BATCH_KNOBS["schedule"])
+    assert not any(x.startswith("per_graph") for x in at.KNOBS["schedule"])  # single graphs: one graph, one decision
 
 
 def test_table_roundtrip_and_nearest(tmp_path):

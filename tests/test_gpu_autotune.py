@@ -70,7 +70,7 @@ def test_tuner_on_a_batch():
     def run(stream, **kw):
         return ip.color_graphs_batched(rp_d, ci_d, node_off, edge_off, stream=stream, **kw)
 
-    knobs = {"workgroups": [0, 32, 256], "schedule": ["hybrid", "data", "hybrid_h10"]}
+    knobs = {"workgroups": [0, 32, 256], "schedule": ["hybrid", "data", "hybrid_h10", "per_graph", "per_graph_h10"]}
     best, ms, dms, trials = at.tune(run, int(node_off[-1]), knobs=knobs, steps=1, warmup=0, passes=1)
     f = at.graph_features(rp_d, node_off)
     assert f["batch"] and f["graphs"] == 24 and f["m"] == int(edge_off[-1])
