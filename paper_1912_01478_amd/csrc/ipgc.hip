@@ -388,6 +388,7 @@ int check_full(Workspace &ws, hipStream_t s, const D &d, int64_t n, int64_t m) {
 template <class D>
 int run(Workspace &ws, int dev, hipStream_t s, const Params &P, D d, int64_t n, int64_t m, int grid,
         int coop, int32_t *out_rounds, ipgc_trace *trace) {
+    using Off = typename D::OffT;
     int64_t span = 0;
     int prep_grid = 0;
     prep_layout(n, &span, &prep_grid);
@@ -488,6 +489,26 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, D d, int64_t n, 
                                            dim3(kRoundBlock), args, 0, s));
         TRY(pf.end(kKindRounds));
         TRY(read_counters(ws, s));
+        if constexpr (D::kSplit) {
+            // per-graph schedules: from resume_round on every graph runs data-driven, which the plain
+            // batch kernel does with fewer registers (same layout, every round data-driven)
+            if (!ws.host_ct->finished && ws.host_ct->resume_round > 0) {
+                static_assert(sizeof(DevT<Off, false>) == sizeof(D), "the two instantiations share one layout");
+                DevT<Off, false> d2;
+                std::memcpy(static_cast<void *>(&d2), &d, sizeof d2);
+                d2.threshold = INT64_MAX;
+                d2.gleft = nullptr;
+                d2.gthr = nullptr;
+                int32_t first2 = ws.host_ct->resume_round;
+                void *args2[] = {&d2, &first2, &last};
+                TRY(clear(ws.bar.p, sizeof(Barrier), s));
+                TRY(pf.begin(kKindRounds));
+                HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rounds<DevT<Off, false>>),
+                                                   dim3(grid), dim3(kRoundBlock), args2, 0, s));
+                TRY(pf.end(kKindRounds));
+                TRY(read_counters(ws, s));
+            }
+        }
     } else {
         for (int32_t r = 1; r <= n + 1; ++r) {
             if (d.discard) k_rebuild_round<<<grid, kRoundBlock, 0, s>>>(d, r);
@@ -677,8 +698,9 @@ int batch_impl(int64_t graphs, const int64_t *node_off, const int64_t *edge_off,
         d.gsplit = ws.gsplit.p;
         d.ngraphs = (int32_t)graphs;
         const int64_t tcap = trace ? std::min<int64_t>(n, std::max<int64_t>(trace->capacity, 0)) : 0;
-        if (tcap > 0) {
+        if (tcap > 0) {  // cleared: rounds left to the plain kernel have no topology-driven graph
             TRY(ws.trace_topo.reserve(tcap));
+            TRY(clear(ws.trace_topo.p, sizeof(int32_t) * tcap, s));
             d.trace_topo = ws.trace_topo.p;
             d.topo_cap = tcap;
         }

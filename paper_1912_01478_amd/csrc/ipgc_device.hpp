@@ -144,6 +144,8 @@ struct Counters {
     int32_t bad_ends;                 // rowptr[0] != 0 or rowptr[n] != m (their values in ends)
     int32_t split_topo;               // per-graph schedules, stepped launches: graphs with active nodes of
     int32_t split_data;               // each kind in the current round (written by its assign launch)
+    int32_t resume_round;             // per-graph schedules: the round from which every graph runs data-driven,
+                                      // left by the per-graph round kernel to the plain one (0: none)
     int64_t ends[2];
 };
 
@@ -2211,7 +2213,6 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
     int G = gridDim.x;        // workgroups in the round loop
     int writers = gridDim.x;  // workgroups that wrote the list this round reads
     bool discarded = false;   // the previous round kept no worklist
-    bool split_live = true;   // per-graph schedules: some graph may still run topology-driven
     for (; r <= last; ++r) {
         if (r > 1) load_segments(d, r & 1, pre, writers);
         RoundIn in = round_view(d, r, pre);
@@ -2222,9 +2223,14 @@ __global__ __launch_bounds__(kRoundBlock) void k_rounds(D d, int32_t first, int3
                 Split sp{0, 0};
                 if (r == 1) {
                     if (blockIdx.x == 0) sp = graph_split(d, true);
-                } else if (split_live) {
+                } else {
                     sp = graph_split(d, false);
-                    split_live = sp.topo > 0;  // gleft only shrinks: a data-driven graph stays data-driven
+                    if (sp.topo == 0) {
+                        // gleft only shrinks, so every graph stays data-driven from here on: the rounds
+                        // left go to the plain batch kernel, which carries none of this code
+                        if (blockIdx.x == 0 && threadIdx.x == 0) d.ct->resume_round = r;
+                        break;
+                    }
                 }
                 if (r > 1) in = graph_round(d, r, pre, sp, &two);
                 if (blockIdx.x == 0 && threadIdx.x == 0 && r - 1 < d.topo_cap) d.trace_topo[r - 1] = sp.topo;
