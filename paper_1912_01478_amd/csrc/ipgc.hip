@@ -672,6 +672,11 @@ int batch_impl(int64_t graphs, const int64_t *node_off, const int64_t *edge_off,
         d.grounds = ws.grounds.p;
         d.c = out_colors_packed;
     };
+    // a workgroup's out segment per class holds (its share + a workgroup) entries, twice that with
+    // per-graph schedules, counted in int32
+    if (((n + grid - 1) / grid + kRoundBlock) * (P.per_graph ? 2 : 1) > INT32_MAX)
+        return fail(IPGC_ETOOBIG, "%lld nodes over %d workgroups overflow a worklist segment; use more workgroups",
+                    (long long)n, grid);
     int32_t rounds = -1;
     std::vector<int32_t> h_thr, h_left;  // per-graph schedules (alive until the call has synchronized)
     if (P.per_graph) {
