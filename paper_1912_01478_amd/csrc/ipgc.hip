@@ -464,7 +464,10 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, D d, int64_t n, 
         const int64_t n_w = ws.host_ct->class_n[kW], n_hub = ws.host_ct->class_n[kM];
         const int64_t hub_chunks = ws.host_ct->hub_chunks;
         TRY(pf.begin(kKindPrep));
-        if (n_w > 0) k_prep_wide<<<(int)std::min<int64_t>(8192, (n_w + 3) / 4), kPrepBlock, 0, s>>>(d);
+        // a wavefront per W node, or a quarter wavefront per node while their rows hold at most 1024 entries
+        const int64_t per_wave = P.hub_min <= 1024 ? 4 : 1;
+        if (n_w > 0)
+            k_prep_wide<<<(int)std::min<int64_t>(8192, (n_w + 4 * per_wave - 1) / (4 * per_wave)), kPrepBlock, 0, s>>>(d);
         if (n_hub > 0) {
             const int blocks = (int)std::min<int64_t>(8192, (hub_chunks + 3) / 4);
             k_prep_hubs<false><<<blocks, kPrepBlock, 0, s>>>(d);
@@ -485,6 +488,15 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, D d, int64_t n, 
         int32_t first = 1, last = (int32_t)std::min<int64_t>(n + 1, INT32_MAX - 2);
         void *args[] = {&d, &first, &last};
         TRY(pf.begin(kKindRounds));
+        // one graph whose nodes all pull: round 1 needs no state reads, in a launch of its own so
+        // that the round kernel does not carry that code
+        if constexpr (!D::kSplit && std::is_same<Off, int32_t>::value) {
+            if (n >= (1 << 20) && d.light_pull == kPullOnly && ws.host_ct->class_n[kL] == n && !d.racy && !d.discard) {
+                k_round1_light<<<grid, kRoundBlock, 0, s>>>(d);
+                HIP_TRY(hipGetLastError());
+                first = 2;
+            }
+        }
         HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_rounds<D>), dim3(grid),
                                            dim3(kRoundBlock), args, 0, s));
         TRY(pf.end(kKindRounds));

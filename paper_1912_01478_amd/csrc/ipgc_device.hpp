@@ -573,13 +573,15 @@ __global__ __launch_bounds__(1024) void k_offsets(D d, int32_t prep_grid) {
         int32_t *row = d.block_cnt + (int64_t)k * prep_grid;
         int32_t sum = 0;
         int64_t ds = 0;
-        for (int32_t b = b0; b < b1; ++b) {
+#pragma unroll 8
+        for (int32_t b = b0; b < b1; ++b) {  // unrolled: eight loads in flight, not one
             sum += row[b];
             if (k < kNumClasses) ds += d.block_deg[(int64_t)k * prep_grid + b];
         }
         int tot;
         const int ex = block_scan(sum, &tot);
         int32_t acc = (k < kNumClasses ? base : 0) + ex;
+#pragma unroll 8
         for (int32_t b = b0; b < b1; ++b) {
             const int32_t x = row[b];
             row[b] = acc;
@@ -725,6 +727,53 @@ __device__ void ring_build_wave(const D &d, int32_t v, int64_t lo, int64_t hi, i
     }
 }
 
+// The same ring and checks for four W nodes at once, a quarter wavefront (16 lanes) each, for rows
+// of at most 1024 entries, where a wavefront per node would leave most of its lanes idle.  The
+// pass loop runs for the longest of the four rows; has: this quarter holds a node.
+template <class D>
+__device__ __forceinline__ void ring_build_quarter(const D &d, int32_t v, bool has, int &bad, int &unsorted) {
+    constexpr int Q = 16, P = kRingPass;
+    const int lane = lane_id(), grp = lane / Q, gl = lane % Q;
+    int64_t b = 0, e = 0, lo = 0, hi = 0;
+    if (has) {
+        b = d.rowptr[v];
+        e = d.rowptr[v + 1];
+        lo = d.base(v);
+        hi = d.id_end(v);
+    }
+    int64_t len = e - b;
+    len = max(len, (int64_t)__shfl_xor((long long)len, 16));
+    len = max(len, (int64_t)__shfl_xor((long long)len, 32));
+    const uint64_t mine = 0xFFFFull << (grp * Q), below = ((1ull << gl) - 1) << (grp * Q);
+    int32_t nl = 0;
+    for (int64_t k0 = 0; k0 < len; k0 += P * Q) {
+        int64_t ug[P], nx[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const int64_t k = b + k0 + j * Q + gl;
+            ug[j] = k < e ? (int64_t)d.colidx[k] + lo : -1;
+            nx[j] = k + 1 < e ? (int64_t)d.colidx[k + 1] + lo : INT64_MAX;
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const int64_t k = b + k0 + j * Q + gl;
+            const bool ok = ug[j] >= lo && ug[j] < hi;
+            if (k < e) {
+                bad |= !ok;
+                unsorted |= nx[j] <= ug[j];
+            }
+            const bool sel = ok && (int32_t)ug[j] < v;
+            const uint64_t m = __ballot(sel) & mine;
+            if (sel) d.lower[b + nl + __popcll(m & below)] = (int32_t)ug[j];
+            nl += __popcll(m);
+        }
+    }
+    if (has && gl == 0) {
+        d.lstart[v] = 0;
+        d.llen[v] = nl;
+    }
+}
+
 // Node at position i of class k's static list (0, 1, ..., n-1 when one class
 // holds every node and the list is not written).
 template <class D>
@@ -741,9 +790,18 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep_wide(D d) {
     const int64_t nw = (int64_t)gridDim.x * blockDim.x / kWave;
     const int32_t nWide = d.ct->class_n[kW] + (d.hub_pre ? 0 : d.ct->class_n[kM]);
     int bad = 0, unsorted = 0;
-    for (int64_t i = gw; i < nWide; i += nw) {
-        const int32_t v = static_at(d, kW, i);
-        ring_build_wave(d, v, d.base(v), d.id_end(v), bad, unsorted);
+    if (d.hub_pre && d.hub_min <= 1024) {  // only class W here, rows of at most 1024 entries
+        const int grp = lane_id() / 16;
+        for (int64_t i0 = gw * 4; i0 < nWide; i0 += nw * 4) {  // the same for the whole wavefront
+            const int64_t i = i0 + grp;
+            const bool has = i < nWide;
+            ring_build_quarter(d, has ? static_at(d, kW, i) : 0, has, bad, unsorted);
+        }
+    } else {
+        for (int64_t i = gw; i < nWide; i += nw) {
+            const int32_t v = static_at(d, kW, i);
+            ring_build_wave(d, v, d.base(v), d.id_end(v), bad, unsorted);
+        }
     }
     if (__ballot(bad) && lane_id() == 0) d.ct->bad_ids = 1;
     if (__ballot(unsorted) && lane_id() == 0) d.ct->unsorted = 1;
@@ -1391,7 +1449,9 @@ __device__ __forceinline__ void light_assign(const D &d, const ClassView &cv, bo
 }
 
 
-template <bool TOPO, class D>
+// R1: round 1 of a graph whose nodes all pull (k_round1_light): every node holds tentative color
+// 1, so a node loses iff it has a smaller neighbour, and no state is read.
+template <bool TOPO, class D, bool R1 = false>
 __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, bool split, int64_t seg_base, bool discard,
                                                int32_t r, Units &un, int G, int32_t *list, int32_t seg_cap,
                                                int *s_cnt, unsigned long long *s_deg) {
@@ -1420,7 +1480,7 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
             if (split) drop_other_part<TOPO>(d, v, act);
         }
     #pragma unroll
-        for (int j = 0; j < K; ++j) t[j] = v[j] >= 0 ? -d.c[v[j]] : 0;
+        for (int j = 0; j < K; ++j) t[j] = v[j] >= 0 ? (R1 ? 1 : -d.c[v[j]]) : 0;
         if (TOPO) {
     #pragma unroll
             for (int j = 0; j < K; ++j)
@@ -1463,7 +1523,7 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
     #pragma unroll
             for (int j = 0; j < K; ++j)
     #pragma unroll
-                for (int q = 0; q < C; ++q) cu[j][q] = u[j][q] < v[j] ? d.c[u[j][q]] : 0;
+                for (int q = 0; q < C; ++q) cu[j][q] = u[j][q] < v[j] ? (R1 ? -1 : d.c[u[j][q]]) : 0;
     #pragma unroll
             for (int j = 0; j < K; ++j) {
     #pragma unroll
@@ -2344,6 +2404,38 @@ __global__ __launch_bounds__(kRoundBlock) void k_conflict_round(D d, int32_t r) 
     Units un;
     conflict_step(d, in, out_segs(d, r), r, un, gridDim.x, two ? 1 : 0);
     if (two) conflict_step(d, sweep_view(d, r, pre), out_segs(d, r), r, un, gridDim.x, 2);
+    un.flush(d);
+}
+
+// Round 1 of a graph whose nodes are all of class L and pull their neighbours' colors, as a launch of
+// its own before the cooperative round kernel (which then starts at round 2): light_conflict's
+// round-1 form over the static list, losers into this workgroup's segments, as k_rounds' round 1
+// would leave them.  The grid is the round kernel's.
+template <class D>
+__global__ __launch_bounds__(kRoundBlock) void k_round1_light(D d) {
+    if (input_bad(d.ct)) return;
+    __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];  // not read: round 1 reads the static list
+    __shared__ int s_cnt[kNumClasses];
+    __shared__ unsigned long long s_deg[kNumClasses];
+    const RoundIn in = round_view(d, 1, pre);
+    if (blockIdx.x == 0) round_record(d, 1, in, true, gridDim.x);
+    if (in.total == 0) return;
+    tick(d, 0);
+    tick(d, 1);
+    Units un;
+    if (threadIdx.x < kNumClasses) {
+        s_cnt[threadIdx.x] = 0;
+        s_deg[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    const OutSegs os = out_segs(d, 1);
+    light_conflict<true, D, true>(d, in.cv[kL], false, os.cls_off[kL] + (int64_t)blockIdx.x * os.cap[kL], false, 1, un,
+                                  gridDim.x, os.list, os.cap[kL], s_cnt, s_deg);
+    __syncthreads();
+    if (threadIdx.x < kNumClasses) {
+        os.cnt[threadIdx.x * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
+        os.deg[threadIdx.x * gridDim.x + blockIdx.x] = (int64_t)s_deg[threadIdx.x];
+    }
     un.flush(d);
 }
 
