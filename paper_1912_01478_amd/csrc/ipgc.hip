@@ -445,7 +445,6 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, D d, int64_t n, 
 
     TRY(clear(ws.bar.p, sizeof(Barrier), s));
     TRY(clear(ws.units.p, sizeof(int64_t) * kNumUnits * grid, s));
-    TRY(clear(ws.F.p, (size_t)(m + n + 64), s));  // every byte map starts empty
     TRY(pf.begin(kKindInit));
     k_init<<<prep_grid, kPrepBlock, 0, s>>>(d, ws.cls.p, (int32_t)span, P.check_ids ? 1 : 0);
     k_offsets<<<1, 1024, 0, s>>>(d, prep_grid);
@@ -455,6 +454,9 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, D d, int64_t n, 
     TRY(read_counters(ws, s));
     TRY(row_verdict(*ws.host_ct, m));
     const int64_t n_wide = (int64_t)ws.host_ct->class_n[kW] + ws.host_ct->class_n[kM];
+    // byte maps hold colors above 64, which only W/M nodes (degree above 63) can need: every map
+    // starts empty when such nodes exist, and none is read otherwise
+    if (n_wide > 0) TRY(clear(ws.F.p, (size_t)(m + n + 64), s));
     if (P.light == 0 || (P.light < 0 && n_wide > 0)) d.light_pull = kPushAll;
     else d.light_pull = n_wide > 0 ? kPullLight : kPullOnly;
     d.racy = P.racy ? 1 : 0;
@@ -477,7 +479,9 @@ int run(Workspace &ws, int dev, hipStream_t s, const Params &P, D d, int64_t n, 
         HIP_TRY(hipGetLastError());
     }
     if (P.check_ids) {
-        TRY(read_counters(ws, s));
+        // the ring building of W/M rows checks their ids; with none, k_init's checks of the light
+        // rows were all, and the counters read above hold them
+        if (n_wide > 0) TRY(read_counters(ws, s));
         if (ws.host_ct->bad_ids) return fail(IPGC_EBADCSR, "a column id is outside [0, n)");
     }
     d.sorted = P.check_ids && !ws.host_ct->unsorted;
