@@ -285,3 +285,52 @@ def test_full_size_against_oracle_digest(cfg):
         assert rounds == d["rounds"]
         assert _sha(wl.astype(np.int32)) == d["wl_sizes_sha256"]
         assert _sha(col) == d["colors_sha256"]
+
+
+# Graphs of at least 2^20 nodes that are all light and pull their colors run round 1 as a launch
+# of its own (every node holds tentative color 1, so a node loses iff it has a smaller neighbour)
+# before the round kernel, which starts at round 2.
+ROAD_1M = gg.road_knn(1_100_000, gg.key(203, 0), name="road1p1m")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_round1_launch_all_light_graph(mode):
+    assert int(np.diff(ROAD_1M.rowptr).max()) <= 32  # every node light: the round-1 launch runs
+    assert_parity(ROAD_1M, mode, ref=_road_ref())
+
+
+def _road_ref():
+    if not hasattr(_road_ref, "ref"):
+        _road_ref.ref = oracle.color_graph(ROAD_1M.rowptr, ROAD_1M.colidx)
+    return _road_ref.ref
+
+
+@pytest.mark.parametrize("kw", [dict(stepped=True), dict(light="push"), dict(workgroups=7),
+                                dict(validate=0), dict(tail_workgroups=-1)],
+                         ids=["stepped", "push", "wg7", "novalidate", "alltail"])
+def test_round1_launch_against_other_paths(kw):
+    """The paths without the round-1 launch (stepped, pushes) and odd grids give the same bits."""
+    assert_parity(ROAD_1M, "hybrid", ref=_road_ref(), **kw)
+
+
+def test_round1_launch_unsorted_rows():
+    rp, ci = gg.shuffle_rows(ROAD_1M, 5)
+    assert_parity(ROAD_1M, "hybrid", ref=_road_ref(), rowptr=rp, colidx=ci)
+
+
+def test_round1_launch_edgeless_and_timeline():
+    import paper_1912_01478_amd as ip
+    n = (1 << 20) + 3
+    g = gg.empty(n)
+    col, rounds, wl, _ = gpu(g, "hybrid")
+    assert rounds == 1 and (col == 1).all() and list(wl) == [n]
+    rp = torch.from_numpy(ROAD_1M.rowptr).cuda()
+    ci = torch.from_numpy(ROAD_1M.colidx).cuda()
+    ref = _road_ref()
+    res = ip.color_graph(rp, ci, "hybrid", profile_mask=0xFFFF, timeline=3 * ref.rounds + 4)
+    torch.cuda.synchronize()
+    assert res.rounds == ref.rounds
+    k = res.profile["kernels"]["rounds"]
+    assert k["launches"] == 1  # one bracket around the round-1 launch and the round kernel
+    ph = res.profile["phase_ticks"]
+    assert ph[0] > 0 and ph[3] >= ph[0]  # round 1 started (its own launch), round 2 after it
