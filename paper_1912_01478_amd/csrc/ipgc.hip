@@ -17,13 +17,15 @@
 //                 their rows
 //   k_prep_hubs   the same for class-M nodes, a row chunk per wavefront (a
 //                 counting launch, then a placing launch)
-//   k_rounds      every round, one cooperative launch with grid barriers
-//                 (or k_assign_round + k_conflict_round + k_push_round per
-//                 round when stepped)
+//   k_round1_light  round 1 of a graph of at least 2^20 nodes that are all light
+//                 and pull their colors (no state read), before the round kernel
+//   k_rounds      every round (from round 2 after k_round1_light), one
+//                 cooperative launch with grid barriers (or k_assign_round +
+//                 k_conflict_round + k_push_round per round when stepped)
 // and read back the round count.  The host synchronizes after k_fill_static
 // (class counts decide the launches that follow; a node's row is only read
-// through its own checked row pointers), after the ring building (the column
-// checks decide whether to go on) and after the rounds.
+// through its own checked row pointers), after the ring building when there is
+// one (the column checks decide whether to go on) and after the rounds.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
