@@ -107,7 +107,7 @@ def test_arrivals_while_running():
 
 
 def test_alone_and_in_the_mix_agree():
-    """The benchmark spec's serving check: each job's result alone equals its result in the mix."""
+    """The serving check: each job's result alone equals its result in the mix."""
     import paper_1912_01478_amd as ip
     probe = [gg.config_graph(2, scale_down=8), gg.batch_graph(4, 3, 1e3, 2e4), gg.complete(300)]
     alone = {}
