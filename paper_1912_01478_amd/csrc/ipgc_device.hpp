@@ -1449,9 +1449,7 @@ __device__ __forceinline__ void light_assign(const D &d, const ClassView &cv, bo
 }
 
 
-// R1: round 1 of a graph whose nodes all pull (k_round1_light): every node holds tentative color
-// 1, so a node loses iff it has a smaller neighbour, and no state is read.
-template <bool TOPO, class D, bool R1 = false>
+template <bool TOPO, class D>
 __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, bool split, int64_t seg_base, bool discard,
                                                int32_t r, Units &un, int G, int32_t *list, int32_t seg_cap,
                                                int *s_cnt, unsigned long long *s_deg) {
@@ -1480,7 +1478,7 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
             if (split) drop_other_part<TOPO>(d, v, act);
         }
     #pragma unroll
-        for (int j = 0; j < K; ++j) t[j] = v[j] >= 0 ? (R1 ? 1 : -d.c[v[j]]) : 0;
+        for (int j = 0; j < K; ++j) t[j] = v[j] >= 0 ? -d.c[v[j]] : 0;
         if (TOPO) {
     #pragma unroll
             for (int j = 0; j < K; ++j)
@@ -1523,7 +1521,7 @@ __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, 
     #pragma unroll
             for (int j = 0; j < K; ++j)
     #pragma unroll
-                for (int q = 0; q < C; ++q) cu[j][q] = u[j][q] < v[j] ? (R1 ? -1 : d.c[u[j][q]]) : 0;
+                for (int q = 0; q < C; ++q) cu[j][q] = u[j][q] < v[j] ? d.c[u[j][q]] : 0;
     #pragma unroll
             for (int j = 0; j < K; ++j) {
     #pragma unroll
@@ -2407,34 +2405,121 @@ __global__ __launch_bounds__(kRoundBlock) void k_conflict_round(D d, int32_t r) 
     un.flush(d);
 }
 
-// Round 1 of a graph whose nodes are all of class L and pull their neighbours' colors, as a launch of
-// its own before the cooperative round kernel (which then starts at round 2): light_conflict's
-// round-1 form over the static list, losers into this workgroup's segments, as k_rounds' round 1
-// would leave them.  The grid is the round kernel's.
+// Round 1 of a graph whose nodes are all of class L and pull their neighbours' colors (so the static
+// list is the identity), as a launch of its own before the cooperative round kernel, which then
+// starts at round 2.  Every node holds tentative color 1, so node v loses iff it has a smaller
+// neighbour: with sorted rows the row's first entry decides, otherwise the whole row is read; no
+// state is read.  Winners commit color 1; losers go to this workgroup's class-L segment, as the
+// round kernel's round 1 leaves them.  Blocks of 64 * K nodes go round the workgroups of the round
+// kernel's grid, so no workgroup takes more than n / G + 64 * K * (1 + 1/G) nodes: its segment holds
+// them.  Eight nodes per lane keep many row reads in flight (this step has no other work).
 template <class D>
 __global__ __launch_bounds__(kRoundBlock) void k_round1_light(D d) {
+    constexpr int K = 8;
+    static_assert(2 * kWave * K <= kRoundBlock, "a workgroup's share fits its out segment");
     if (input_bad(d.ct)) return;
     __shared__ int32_t pre[kNumClasses][kMaxRoundBlocks + 1];  // not read: round 1 reads the static list
-    __shared__ int s_cnt[kNumClasses];
-    __shared__ unsigned long long s_deg[kNumClasses];
+    __shared__ int s_cnt;
+    __shared__ unsigned long long s_deg;
     const RoundIn in = round_view(d, 1, pre);
     if (blockIdx.x == 0) round_record(d, 1, in, true, gridDim.x);
+    const int64_t n = in.cv[kL].total;
     if (in.total == 0) return;
     tick(d, 0);
     tick(d, 1);
     Units un;
-    if (threadIdx.x < kNumClasses) {
-        s_cnt[threadIdx.x] = 0;
-        s_deg[threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        s_cnt = 0;
+        s_deg = 0;
     }
     __syncthreads();
     const OutSegs os = out_segs(d, 1);
-    light_conflict<true, D, true>(d, in.cv[kL], false, os.cls_off[kL] + (int64_t)blockIdx.x * os.cap[kL], false, 1, un,
-                                  gridDim.x, os.list, os.cap[kL], s_cnt, s_deg);
+    const int64_t seg = os.cls_off[kL] + (int64_t)blockIdx.x * os.cap[kL];
+    const int lane = lane_id();
+    const int64_t gw = (int64_t)(threadIdx.x / kWave) * gridDim.x + blockIdx.x;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t b0 = gw * (kWave * K); b0 < n; b0 += nw * (kWave * K)) {
+        int64_t a[K], e[K];
+        uint32_t act = 0, lose = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int64_t v = b0 + j * kWave + lane;
+            act |= (v < n ? 1u : 0u) << j;
+            a[j] = v < n ? (int64_t)d.rowptr[v] : 0;
+            e[j] = v < n ? (int64_t)d.rowptr[v + 1] : 0;
+        }
+        int32_t read = 0;
+        if (d.sorted) {  // the first entry is the row's smallest
+            int64_t u[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) u[j] = a[j] < e[j] ? (int64_t)d.colidx[a[j]] + d.base((int32_t)(b0 + j * kWave + lane)) : INT64_MAX;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                lose |= (u[j] < b0 + j * kWave + lane ? 1u : 0u) << j;
+                read += a[j] < e[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int64_t v = b0 + j * kWave + lane;
+                const int64_t base = v < n ? d.base((int32_t)v) : 0;
+                for (int64_t k0 = a[j]; k0 < e[j]; k0 += 4) {
+                    int64_t u[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) u[q] = k0 + q < e[j] ? (int64_t)d.colidx[k0 + q] + base : INT64_MAX;
+                    bool hit = false;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) hit |= u[q] < v;
+                    read += (int32_t)min<int64_t>(4, e[j] - k0);
+                    if (hit) {
+                        lose |= 1u << j;
+                        break;
+                    }
+                }
+            }
+        }
+        lose &= act;
+        // losers: one shared-memory atomic per wavefront for their slots, one for their degrees
+        int nl = 0;
+        int64_t ldeg = 0;
+        uint64_t lm[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            lm[j] = __ballot(lose >> j & 1u);
+            nl += __popcll(lm[j]);
+            ldeg += lose >> j & 1u ? e[j] - a[j] : 0;
+        }
+        if (nl) {
+            const int64_t dsum = wave_sum(ldeg);
+            int slot = 0;
+            if (lane == 0) {
+                slot = atomicAdd(&s_cnt, nl);
+                atomicAdd(&s_deg, (unsigned long long)dsum);
+            }
+            slot = __shfl(slot, 0);
+            if (slot + nl > os.cap[kL]) {  // cannot happen (see above); reported instead of written
+                if (lane == 0) d.ct->seg_overflow = 1;
+            } else {
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    if (lose >> j & 1u) os.list[seg + slot + __popcll(lm[j] & lanes_below())] = (int32_t)(b0 + j * kWave + lane);
+                    slot += __popcll(lm[j]);
+                }
+            }
+        }
+        // winners commit color 1
+        const uint32_t win = act & ~lose;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (win >> j & 1u) d.c[b0 + j * kWave + lane] = 1;
+        un.u[kUCommits] += __popc(win);
+        un.u[kUConflictNodes] += __popc(act);
+        un.u[kUConflictEntries] += read;
+    }
     __syncthreads();
     if (threadIdx.x < kNumClasses) {
-        os.cnt[threadIdx.x * gridDim.x + blockIdx.x] = s_cnt[threadIdx.x];
-        os.deg[threadIdx.x * gridDim.x + blockIdx.x] = (int64_t)s_deg[threadIdx.x];
+        os.cnt[threadIdx.x * gridDim.x + blockIdx.x] = threadIdx.x == kL ? s_cnt : 0;
+        os.deg[threadIdx.x * gridDim.x + blockIdx.x] = threadIdx.x == kL ? (int64_t)s_deg : 0;
     }
     un.flush(d);
 }
