@@ -1273,8 +1273,6 @@ __device__ __forceinline__ void map_assign_wave(const D &d, int32_t v, Units &un
 // kLightK * kLightC loads outstanding where a node alone has a chain of dependent ones.  A
 // wavefront takes items b0 + j * 64 + lane (j < kLightK) of a block of 64 * kLightK consecutive
 // items, so every load of a step is coalesced across the wavefront when the items are.
-// Per-graph schedules, a round of both kinds: the light items of graphs handled by the other
-// pass become absent (no node, not active).
 constexpr int kLightK = 2;  // nodes per lane
 constexpr int kLightC = 4;  // row entries per node per pass
 
@@ -1360,7 +1358,10 @@ struct LightIter<true> {
     }
 };
 
-
+// Tentative colors of the class-L items (Section II-C, first fit): the first zero bit of the
+// node's color mask (push modes: committed neighbours set bit t - 1; d <= 32 neighbours leave a
+// zero among the first 33 bits), or of a mask of the committed colors read from the
+// neighbours' states (pull modes).  TOPO: a sweep over the static list, committed nodes skipped.
 template <bool TOPO, class D>
 __device__ __forceinline__ void light_assign(const D &d, const ClassView &cv, bool split, Units &un, int G) {
     using Off = typename D::OffT;
@@ -1448,7 +1449,13 @@ __device__ __forceinline__ void light_assign(const D &d, const ClassView &cv, bo
     }
 }
 
-
+// Conflict test, commit and push of the class-L items (Section II-C): v loses iff a smaller
+// neighbour holds its tentative color t.  Pull-only graphs scan the row up to v (sorted rows
+// stop there); push modes scan only the positions still pending, and drop from them the
+// neighbours found committed (their colors have reached v's mask).  Losers go to the
+// workgroup's class-L segment with one shared-memory atomic per wavefront (ballot and popcount
+// give each its slot); winners commit and, in push modes, set bit t - 1 (t <= 33) in their
+// neighbours' masks.
 template <bool TOPO, class D>
 __device__ __forceinline__ void light_conflict(const D &d, const ClassView &cv, bool split, int64_t seg_base, bool discard,
                                                int32_t r, Units &un, int G, int32_t *list, int32_t seg_cap,
