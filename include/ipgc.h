@@ -257,10 +257,13 @@ int ipgc_color_graph_noalloc(const int32_t *csr_rowptr, const int32_t *csr_colid
  * out_colors_packed DEVICE, N int32 entries: graph g's colors at out_colors_packed + node_off[g].
  * out_rounds     HOST, G entries: each graph's round count (-1 for all on error).
  * trace          optional (NULL: none): per round of the whole batch, the size and degree sum of
- *                the union of the graphs' worklists and the kind of round run.
+ *                the union of the graphs' worklists and the kind of round run (with
+ *                IPGC_FLAG_PER_GRAPH also topo_graphs: the graphs that ran it topology-driven).
  * Every local row pointer sequence is checked (starts at 0, non-decreasing, ends at the graph's
  * entry count) at every validation level; column ids are checked against their own graph's node
- * count unless validation is IPGC_VALIDATE_NONE.  Options, stream and blocking are as for
+ * count unless validation is IPGC_VALIDATE_NONE.  IPGC_ETOOBIG if options->workgroups is so small
+ * that a workgroup's worklist segment (N / workgroups + 1024 entries, twice that with
+ * IPGC_FLAG_PER_GRAPH) would pass INT32_MAX.  Options, stream and blocking are as for
  * ipgc_color_graph_ex; the round limit is the batch's node count.
  */
 int ipgc_color_graphs_batched(int64_t num_graphs, const int64_t *node_off, const int64_t *edge_off,
